@@ -1,0 +1,229 @@
+"""CPU oracle for exact hypercube convolution -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The product package never imports it
+and shares no code with it.
+
+Wraps ``oracle/hc_oracle.c`` (plain C, built with ``-ffp-contract=off``) with
+numpy arrays:
+
+* ``naive``      -- Algorithm 1 (naive Cartesian product) on hypercubes.
+* ``canonical``  -- the method in per-axis form: forward map on axes
+  0..D-1, elementwise product, inverse map on axes D-1..0 (Methods section,
+  three-subproblem recursion, unrolled over all axes).
+* ``recursive``  -- the three-subproblem recursion itself (memory-light).
+* ``adjoint``    -- gradient of ``sum(w * z)`` by transposed maps.
+* ``direct_at`` / ``correlation_at`` -- the definitions evaluated at chosen
+  indices with compensated long double sums.
+* ``bound`` / ``adjoint_bound`` -- magnitudes B with
+  ``|computed - exact| <= (4D + 2) u B``.
+
+dtype is taken from the inputs: float64, float32 or int64 (int64 arithmetic
+wraps modulo 2^64, which is exact whenever the true result fits in int64).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liboracle.so")
+SOURCES = [os.path.join(_HERE, "hc_oracle.c"), os.path.join(_HERE, "hc_oracle_impl.h")]
+
+CFLAGS = ["-O2", "-std=c11", "-Wall", "-Wextra", "-ffp-contract=off", "-fno-fast-math",
+          "-fopenmp", "-fPIC", "-shared"]
+
+_lib = None
+
+
+def build() -> str:
+    """Compile the oracle shared library with gcc (always recompiles)."""
+    tmp = LIB_PATH + ".tmp"
+    cmd = ["gcc", *CFLAGS, "-o", tmp, SOURCES[0], "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, LIB_PATH)
+    return LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        build()
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    I = ctypes.c_int
+    I64 = ctypes.c_int64
+    for sfx in ("f64", "f32", "i64"):
+        for name, args in (("hco_naive_", [P, P, P, I]),
+                           ("hco_canonical_", [P, P, P, I]),
+                           ("hco_recursive_", [P, P, P, I, I]),
+                           ("hco_adjoint_", [P, P, P, P, P, I])):
+            fn = getattr(lib, name + sfx)
+            fn.argtypes = args
+            fn.restype = I
+    lib.hco_pow3.argtypes = [I]
+    lib.hco_pow3.restype = ctypes.c_uint64
+    lib.hco_tern.argtypes = [ctypes.c_uint64]
+    lib.hco_tern.restype = ctypes.c_uint64
+    lib.hco_tern_map.argtypes = [I, P]
+    lib.hco_tern_map.restype = None
+    lib.hco_direct_at_f64.argtypes = [P, P, I, P, I64, P]
+    lib.hco_direct_at_f64.restype = None
+    lib.hco_direct_at_i64.argtypes = [P, P, I, P, I64, P]
+    lib.hco_direct_at_i64.restype = None
+    lib.hco_correlation_at_f64.argtypes = [P, P, P, I, P, I64, P, P]
+    lib.hco_correlation_at_f64.restype = None
+    lib.hco_bound_f64.argtypes = [P, P, P, I]
+    lib.hco_bound_f64.restype = I
+    lib.hco_adjoint_bound_f64.argtypes = [P, P, P, P, P, I]
+    lib.hco_adjoint_bound_f64.restype = I
+    _lib = lib
+    return lib
+
+
+_SFX = {np.dtype(np.float64): "f64", np.dtype(np.float32): "f32", np.dtype(np.int64): "i64"}
+
+
+def pow3(n: int) -> int:
+    return 3 ** n
+
+
+def dim_of(x: np.ndarray) -> int:
+    n = int(x.size)
+    D = n.bit_length() - 1
+    if n <= 0 or (1 << D) != n:
+        raise ValueError(f"hypercube input must have 2^D elements, got {n}")
+    return D
+
+
+def _vec(a: np.ndarray) -> np.ndarray:
+    a = np.ascontiguousarray(a).reshape(-1)
+    if a.dtype not in _SFX:
+        raise TypeError(f"unsupported dtype {a.dtype}")
+    return a
+
+
+def _ptr(a: np.ndarray):
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+def _pair(x, y):
+    x, y = _vec(x), _vec(y)
+    if x.dtype != y.dtype or x.size != y.size:
+        raise ValueError("x and y must have the same dtype and size")
+    return x, y, dim_of(x), _SFX[x.dtype]
+
+
+def tern(i: int) -> int:
+    return int(_load().hco_tern(int(i)))
+
+
+def tern_map(D: int) -> np.ndarray:
+    out = np.empty(1 << D, dtype=np.uint64)
+    _load().hco_tern_map(D, _ptr(out))
+    return out
+
+
+def naive(x, y) -> np.ndarray:
+    x, y, D, sfx = _pair(x, y)
+    z = np.empty(3 ** D, dtype=x.dtype)
+    rc = getattr(_load(), "hco_naive_" + sfx)(_ptr(x), _ptr(y), _ptr(z), D)
+    if rc:
+        raise RuntimeError(f"hco_naive_{sfx} failed ({rc})")
+    return z
+
+
+def canonical(x, y) -> np.ndarray:
+    x, y, D, sfx = _pair(x, y)
+    z = np.empty(3 ** D, dtype=x.dtype)
+    rc = getattr(_load(), "hco_canonical_" + sfx)(_ptr(x), _ptr(y), _ptr(z), D)
+    if rc:
+        raise RuntimeError(f"hco_canonical_{sfx} failed ({rc})")
+    return z
+
+
+def recursive(x, y, threads: int = 1, out: np.ndarray | None = None) -> np.ndarray:
+    x, y, D, sfx = _pair(x, y)
+    if out is None:
+        out = np.empty(3 ** D, dtype=x.dtype)
+    if out.dtype != x.dtype or out.size != 3 ** D or not out.flags.c_contiguous:
+        raise ValueError("bad output buffer")
+    rc = getattr(_load(), "hco_recursive_" + sfx)(_ptr(x), _ptr(y), _ptr(out), D, int(threads))
+    if rc:
+        raise RuntimeError(f"hco_recursive_{sfx} failed ({rc})")
+    return out
+
+
+def adjoint(x, y, w):
+    x, y, D, sfx = _pair(x, y)
+    w = _vec(w)
+    if w.dtype != x.dtype or w.size != 3 ** D:
+        raise ValueError("w must have 3^D elements of the input dtype")
+    gx = np.empty(1 << D, dtype=x.dtype)
+    gy = np.empty(1 << D, dtype=x.dtype)
+    rc = getattr(_load(), "hco_adjoint_" + sfx)(_ptr(x), _ptr(y), _ptr(w), _ptr(gx), _ptr(gy), D)
+    if rc:
+        raise RuntimeError(f"hco_adjoint_{sfx} failed ({rc})")
+    return gx, gy
+
+
+def direct_at(x, y, ks) -> np.ndarray:
+    x, y, D, sfx = _pair(x, y)
+    ks = np.ascontiguousarray(ks, dtype=np.uint64).reshape(-1)
+    if ks.size and int(ks.max()) >= 3 ** D:
+        raise ValueError("output index out of range")
+    if sfx == "f32":
+        raise TypeError("direct_at supports float64 and int64")
+    out = np.empty(ks.size, dtype=x.dtype)
+    getattr(_load(), "hco_direct_at_" + sfx)(_ptr(x), _ptr(y), D, _ptr(ks), ks.size, _ptr(out))
+    return out
+
+
+def correlation_at(x, y, w, idx):
+    x, y, D, sfx = _pair(x, y)
+    if sfx != "f64":
+        raise TypeError("correlation_at supports float64")
+    w = _vec(w)
+    idx = np.ascontiguousarray(idx, dtype=np.uint64).reshape(-1)
+    if idx.size and int(idx.max()) >= (1 << D):
+        raise ValueError("input index out of range")
+    gx = np.empty(idx.size, dtype=np.float64)
+    gy = np.empty(idx.size, dtype=np.float64)
+    _load().hco_correlation_at_f64(_ptr(x), _ptr(y), _ptr(w), D, _ptr(idx), idx.size,
+                                   _ptr(gx), _ptr(gy))
+    return gx, gy
+
+
+def bound(x, y) -> np.ndarray:
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    x, y, D, _ = _pair(x, y)
+    b = np.empty(3 ** D, dtype=np.float64)
+    _load().hco_bound_f64(_ptr(x), _ptr(y), _ptr(b), D)
+    return b
+
+
+def adjoint_bound(x, y, w):
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    x, y, D, _ = _pair(x, y)
+    w = _vec(np.asarray(w, dtype=np.float64))
+    bx = np.empty(1 << D, dtype=np.float64)
+    by = np.empty(1 << D, dtype=np.float64)
+    _load().hco_adjoint_bound_f64(_ptr(x), _ptr(y), _ptr(w), _ptr(bx), _ptr(by), D)
+    return bx, by
+
+
+def unit_roundoff(dtype) -> float:
+    """u for the dtype's arithmetic (0 for int64, which is exact modulo 2^64)."""
+    dt = np.dtype(dtype)
+    if dt == np.float64:
+        return 2.0 ** -53
+    if dt == np.float32:
+        return 2.0 ** -24
+    return 0.0

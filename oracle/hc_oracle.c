@@ -1,0 +1,260 @@
+/*
+ * CPU oracle for exact hypercube convolution {0,1}^D x {0,1}^D -> 3^D
+ * (Serang, "An exact, cache-localized algorithm for the sub-quadratic
+ * convolution of hypercubes").
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library includes, links
+ * or calls this file; only the tests, the smoke check and the benchmark's CPU
+ * baseline load it.  It shares no code, header or table with the GPU path.
+ *
+ * Plain, slow, obviously correct C.  Built with -O2 -ffp-contract=off and no
+ * fast-math, so every floating-point operation is a separately rounded IEEE
+ * operation in the order written.
+ *
+ * Exported functions (per element type, suffix f64 / f32 / i64):
+ *   hco_naive_*      Algorithm 1 (naive Cartesian product)
+ *   hco_canonical_*  the method, per-axis form, full-size scratch
+ *   hco_recursive_*  the method, three-subproblem recursion, memory-light
+ *   hco_adjoint_*    transposed maps (gradient of sum(w * z))
+ * plus fp64/long double helpers for pins: the ternary index map, the direct
+ * per-element definition sum, the direct correlation gradient and the
+ * rounding-error bound.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+uint64_t hco_pow3(int n)
+{
+    uint64_t r = 1;
+    for (int i = 0; i < n; ++i) r *= 3;
+    return r;
+}
+
+/* Packed boolean index -> ternary index with the same digits (Introduction:
+ * the D boolean coordinates fit one machine integer; Discussion: bit i of
+ * the flat index is one axis).  Bit d (weight 2^d) becomes digit d (weight
+ * 3^d); axis 0 is the most significant in both. */
+void hco_tern_map(int D, uint64_t* out)
+{
+    const uint64_t n2 = (uint64_t)1 << D;
+    for (uint64_t i = 0; i < n2; ++i) {
+        uint64_t t = 0, p = 1;
+        for (int d = 0; d < D; ++d) {
+            if ((i >> d) & 1u) t += p;
+            p *= 3;
+        }
+        out[i] = t;
+    }
+}
+
+uint64_t hco_tern(uint64_t i)
+{
+    uint64_t t = 0, p = 1;
+    while (i) {
+        if (i & 1u) t += p;
+        p *= 3;
+        i >>= 1;
+    }
+    return t;
+}
+
+#define ELEM double
+#define SFX f64
+#include "hc_oracle_impl.h"
+#undef ELEM
+#undef SFX
+
+#define ELEM float
+#define SFX f32
+#include "hc_oracle_impl.h"
+#undef ELEM
+#undef SFX
+
+#define ELEM uint64_t
+#define SFX i64
+#include "hc_oracle_impl.h"
+#undef ELEM
+#undef SFX
+
+/* Neumaier-compensated accumulation in long double. */
+typedef struct { long double s, c; } hco_acc;
+static void hco_acc_add(hco_acc* a, long double v)
+{
+    const long double t = a->s + v;
+    if (fabsl(a->s) >= fabsl(v)) a->c += (a->s - t) + v;
+    else a->c += (v - t) + a->s;
+    a->s = t;
+}
+
+/* Definition of convolution (Introduction) evaluated at single output
+ * indices: z[k] = sum over (i, j) with tern(i) + tern(j) = k of x[i]*y[j].
+ * Digit 0 of k admits only bits (0,0), digit 2 only (1,1), digit 1 either
+ * (0,1) or (1,0), so z[k] has 2^(number of 1 digits) terms; they are summed
+ * with compensation in long double.  out[r] receives z[ks[r]]. */
+void hco_direct_at_f64(const double* x, const double* y, int D,
+                       const uint64_t* ks, int64_t n, double* out)
+{
+    for (int64_t r = 0; r < n; ++r) {
+        uint64_t k = ks[r];
+        uint64_t base_i = 0, base_j = 0;
+        int ones_bits[64];
+        int n_ones = 0;
+        for (int d = 0; d < D; ++d) {
+            const uint64_t digit = k % 3;
+            k /= 3;
+            if (digit == 2) { base_i |= (uint64_t)1 << d; base_j |= (uint64_t)1 << d; }
+            else if (digit == 1) ones_bits[n_ones++] = d;
+        }
+        hco_acc acc = {0.0L, 0.0L};
+        const uint64_t n_terms = (uint64_t)1 << n_ones;
+        for (uint64_t m = 0; m < n_terms; ++m) {
+            uint64_t i = base_i, j = base_j;
+            for (int b = 0; b < n_ones; ++b) {
+                if ((m >> b) & 1u) i |= (uint64_t)1 << ones_bits[b];
+                else j |= (uint64_t)1 << ones_bits[b];
+            }
+            hco_acc_add(&acc, (long double)x[i] * (long double)y[j]);
+        }
+        out[r] = (double)(acc.s + acc.c);
+    }
+}
+
+/* Same definition for int64 data with wrapping uint64 arithmetic. */
+void hco_direct_at_i64(const uint64_t* x, const uint64_t* y, int D,
+                       const uint64_t* ks, int64_t n, uint64_t* out)
+{
+    for (int64_t r = 0; r < n; ++r) {
+        uint64_t k = ks[r];
+        uint64_t base_i = 0, base_j = 0;
+        int ones_bits[64];
+        int n_ones = 0;
+        for (int d = 0; d < D; ++d) {
+            const uint64_t digit = k % 3;
+            k /= 3;
+            if (digit == 2) { base_i |= (uint64_t)1 << d; base_j |= (uint64_t)1 << d; }
+            else if (digit == 1) ones_bits[n_ones++] = d;
+        }
+        uint64_t acc = 0;
+        const uint64_t n_terms = (uint64_t)1 << n_ones;
+        for (uint64_t m = 0; m < n_terms; ++m) {
+            uint64_t i = base_i, j = base_j;
+            for (int b = 0; b < n_ones; ++b) {
+                if ((m >> b) & 1u) i |= (uint64_t)1 << ones_bits[b];
+                else j |= (uint64_t)1 << ones_bits[b];
+            }
+            acc += x[i] * y[j];
+        }
+        out[r] = acc;
+    }
+}
+
+/* Direct correlation gradient of L = sum_k w[k] z[k] at selected input
+ * indices (derived from the definition: dz[tern(i)+tern(j)]/dx[i] = y[j]):
+ *   gx[i] = sum_j w[tern(i) + tern(j)] * y[j]
+ *   gy[j] = sum_i w[tern(i) + tern(j)] * x[i]
+ * Compensated long double sums.  gx_out[r] = gx[idx[r]], gy_out[r] = gy[idx[r]]. */
+void hco_correlation_at_f64(const double* x, const double* y, const double* w, int D,
+                            const uint64_t* idx, int64_t n, double* gx_out, double* gy_out)
+{
+    const uint64_t n2 = (uint64_t)1 << D;
+    uint64_t* t = (uint64_t*)malloc(n2 * sizeof(uint64_t));
+    if (!t) abort();
+    hco_tern_map(D, t);
+    for (int64_t r = 0; r < n; ++r) {
+        const uint64_t ti = t[idx[r]];
+        hco_acc ax = {0.0L, 0.0L}, ay = {0.0L, 0.0L};
+        for (uint64_t j = 0; j < n2; ++j) {
+            hco_acc_add(&ax, (long double)w[ti + t[j]] * (long double)y[j]);
+            hco_acc_add(&ay, (long double)w[t[j] + ti] * (long double)x[j]);
+        }
+        if (gx_out) gx_out[r] = (double)(ax.s + ax.c);
+        if (gy_out) gy_out[r] = (double)(ay.s + ay.c);
+    }
+    free(t);
+}
+
+/* Magnitude that bounds the rounding error of the method (derived by
+ * first-order rounding analysis; the paper states only that the result is
+ * exact when (a + b) - a = b holds):
+ *   B = |G|(F|x| . F|y|),  |G|: (p0, p1, p2) -> (p0, p0 + p1 + p2, p2)
+ * computed with the same memory-light recursion as the method.  For the
+ * per-axis method in precision u,  |z_computed - z_exact| <= (4D + 2) u B. */
+static void hco_bound_rec(const double* x, const double* y, double* b, int D)
+{
+    if (D == 0) { b[0] = fabs(x[0]) * fabs(y[0]); return; }
+    const uint64_t h = (uint64_t)1 << (D - 1);
+    const uint64_t t = hco_pow3(D - 1);
+    double* s = (double*)malloc(2 * h * sizeof(double));
+    if (!s) abort();
+    for (uint64_t i = 0; i < h; ++i) s[i] = fabs(x[i]) + fabs(x[h + i]);
+    for (uint64_t i = 0; i < h; ++i) s[h + i] = fabs(y[i]) + fabs(y[h + i]);
+    hco_bound_rec(x, y, b, D - 1);
+    hco_bound_rec(x + h, y + h, b + 2 * t, D - 1);
+    hco_bound_rec(s, s + h, b + t, D - 1);
+    for (uint64_t k = 0; k < t; ++k) b[t + k] = (b[t + k] + b[k]) + b[2 * t + k];
+    free(s);
+}
+
+int hco_bound_f64(const double* x, const double* y, double* b, int D)
+{
+    if (D < 0 || D > 20) return 1;
+    hco_bound_rec(x, y, b, D);
+    return 0;
+}
+
+/* Magnitude bounding the rounding error of the transposed-map adjoint:
+ *   Bx = |F^T|(|G^T| |w| . F|y|),  By = |F^T|(|G^T| |w| . F|x|)
+ * with |G^T|: (w0, w1, w2) -> (w0 + w1, w1, w2 + w1); same axis orders as the
+ * adjoint.  Either output may be NULL. */
+int hco_adjoint_bound_f64(const double* x, const double* y, const double* w,
+                          double* bx, double* by, int D)
+{
+    if (D < 0 || D > 20) return 1;
+    const uint64_t n2 = (uint64_t)1 << D;
+    double* xa = (double*)malloc(n2 * sizeof(double));
+    double* ya = (double*)malloc(n2 * sizeof(double));
+    const uint64_t n3 = hco_pow3(D);
+    double* W = (double*)malloc(n3 * sizeof(double));
+    double* F = (double*)malloc(n3 * sizeof(double));
+    double* T = (double*)malloc(n3 * sizeof(double));
+    double* A = (double*)malloc(n3 * sizeof(double));
+    if (!xa || !ya || !W || !F || !T || !A) abort();
+    for (uint64_t i = 0; i < n2; ++i) { xa[i] = fabs(x[i]); ya[i] = fabs(y[i]); }
+    for (uint64_t k = 0; k < n3; ++k) W[k] = fabs(w[k]);
+    for (int a = 0; a < D; ++a) {
+        const uint64_t n_hi = hco_pow3(a);
+        const uint64_t n_lo = hco_pow3(D - a - 1);
+        for (uint64_t hi = 0; hi < n_hi; ++hi)
+            for (uint64_t lo = 0; lo < n_lo; ++lo) {
+                const double w0 = W[(hi * 3 + 0) * n_lo + lo];
+                const double w1 = W[(hi * 3 + 1) * n_lo + lo];
+                const double w2 = W[(hi * 3 + 2) * n_lo + lo];
+                W[(hi * 3 + 0) * n_lo + lo] = w0 + w1;
+                W[(hi * 3 + 2) * n_lo + lo] = w2 + w1;
+            }
+    }
+    for (int which = 0; which < 2; ++which) {
+        double* g = which == 0 ? bx : by;
+        if (!g) continue;
+        hco_forward_all_f64(which == 0 ? ya : xa, F, T, D);
+        for (uint64_t k = 0; k < n3; ++k) A[k] = W[k] * F[k];
+        for (int a = D - 1; a >= 0; --a) {
+            const uint64_t n_hi = hco_pow3(a);
+            const uint64_t n_lo = (uint64_t)1 << (D - a - 1);
+            for (uint64_t hi = 0; hi < n_hi; ++hi)
+                for (uint64_t lo = 0; lo < n_lo; ++lo) {
+                    const double g0 = A[(hi * 3 + 0) * n_lo + lo];
+                    const double g1 = A[(hi * 3 + 1) * n_lo + lo];
+                    const double g2 = A[(hi * 3 + 2) * n_lo + lo];
+                    T[(hi * 2 + 0) * n_lo + lo] = g0 + g1;
+                    T[(hi * 2 + 1) * n_lo + lo] = g1 + g2;
+                }
+            double* s = A; A = T; T = s;
+        }
+        for (uint64_t i = 0; i < n2; ++i) g[i] = A[i];
+    }
+    free(xa); free(ya); free(W); free(F); free(T); free(A);
+    return 0;
+}

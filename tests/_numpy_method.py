@@ -1,0 +1,38 @@
+"""A numpy transcription of the per-axis method with switches that plant
+plausible mistakes, used only to show that the pins catch them.  Test helper;
+never used as a reference."""
+from __future__ import annotations
+
+import numpy as np
+
+
+def per_axis(x, y, *, forward_order="asc", inverse_order="desc", assoc="left",
+             sign=-1, drop_p2=False, forward_mid="sum", lsb_first=False):
+    D = int(x.size).bit_length() - 1
+    X = x.copy()
+    Y = y.copy()
+    if lsb_first:
+        X = X.reshape((2,) * D).transpose(tuple(range(D))[::-1]).reshape(-1).copy() if D else X
+        Y = Y.reshape((2,) * D).transpose(tuple(range(D))[::-1]).reshape(-1).copy() if D else Y
+    axes = list(range(D)) if forward_order == "asc" else list(range(D))[::-1]
+    shape = [2] * D
+    for a in axes:
+        def fwd(V):
+            v = V.reshape(int(np.prod(shape[:a], dtype=np.int64)), 2, -1)
+            mid = v[:, 0] + v[:, 1] if forward_mid == "sum" else v[:, 0].copy()
+            return np.stack([v[:, 0], mid, v[:, 1]], axis=1).reshape(-1)
+        X, Y = fwd(X), fwd(Y)
+        shape[a] = 3
+    Z = X * Y
+    inv_axes = list(range(D))[::-1] if inverse_order == "desc" else list(range(D))
+    for a in inv_axes:
+        v = Z.reshape(3 ** a, 3, -1)
+        p0, p1, p2 = v[:, 0].copy(), v[:, 1].copy(), v[:, 2].copy()
+        if drop_p2:
+            v[:, 1] = p1 - p0
+        elif assoc == "left":
+            v[:, 1] = (p1 - p0) + sign * p2
+        else:
+            v[:, 1] = p1 - (p0 + p2)
+        Z = v.reshape(-1)
+    return Z

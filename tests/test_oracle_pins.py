@@ -1,0 +1,231 @@
+"""Pins of the CPU oracle against facts fixed outside it (CPU only).
+
+The oracle (oracle/) is test infrastructure; these tests are what make it
+trustworthy before any GPU result is compared with it.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from tests import pins
+
+DTYPES = [np.float64, np.float32, np.int64]
+IMPLS = {
+    "naive": oracle.naive,
+    "canonical": oracle.canonical,
+    "recursive": oracle.recursive,
+    "recursive_mt": lambda x, y: oracle.recursive(x, y, threads=4),
+}
+EXACT_IMPLS = ["naive", "canonical", "recursive", "recursive_mt"]
+METHOD_IMPLS = ["canonical", "recursive", "recursive_mt"]
+
+
+@pytest.mark.parametrize("impl", EXACT_IMPLS)
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_worked_example(impl, dtype):
+    pins.pin_worked_example(IMPLS[impl], dtype)
+
+
+@pytest.mark.parametrize("impl", EXACT_IMPLS)
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("D", [1, 2, 5, 8, 10])
+def test_deltas(impl, dtype, D):
+    pins.pin_deltas(IMPLS[impl], dtype, D)
+
+
+@pytest.mark.parametrize("impl", EXACT_IMPLS)
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_d0(impl, dtype):
+    pins.pin_d0(IMPLS[impl], dtype)
+
+
+@pytest.mark.parametrize("impl", EXACT_IMPLS)
+def test_d1_base_case_int(impl):
+    pins.pin_d1_int(IMPLS[impl])
+
+
+@pytest.mark.parametrize("impl", METHOD_IMPLS)
+def test_d1_rounding_order(impl):
+    pins.pin_d1_rounding(IMPLS[impl])
+
+
+@pytest.mark.parametrize("impl", EXACT_IMPLS)
+@pytest.mark.parametrize("D", list(range(0, 11)))
+def test_scipy_definition_int(impl, D):
+    pins.pin_scipy_int(IMPLS[impl], D)
+
+
+@pytest.mark.parametrize("impl", EXACT_IMPLS)
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("D", [0, 1, 3, 7, 10])
+def test_all_ones(impl, dtype, D):
+    pins.pin_all_ones(IMPLS[impl], dtype, D)
+
+
+@pytest.mark.parametrize("impl", METHOD_IMPLS)
+@pytest.mark.parametrize("D", [1, 4, 9, 12])
+def test_sum_int(impl, D):
+    pins.pin_sum_int(IMPLS[impl], D)
+
+
+@pytest.mark.parametrize("impl", METHOD_IMPLS)
+@pytest.mark.parametrize("D", [1, 3, 6, 9])
+def test_marginals_int(impl, D):
+    pins.pin_marginals_int(IMPLS[impl], D)
+
+
+@pytest.mark.parametrize("impl", METHOD_IMPLS)
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("D", [1, 5, 11])
+def test_commutative(impl, dtype, D):
+    pins.pin_commutative(IMPLS[impl], dtype, D)
+
+
+@pytest.mark.parametrize("impl", METHOD_IMPLS)
+@pytest.mark.parametrize("D", [2, 7, 10])
+def test_linear_int(impl, D):
+    pins.pin_linear_int(IMPLS[impl], D)
+
+
+@pytest.mark.parametrize("impl", METHOD_IMPLS)
+@pytest.mark.parametrize("D", [1, 4, 9])
+def test_axis_flip_int(impl, D):
+    pins.pin_axis_flip_int(IMPLS[impl], D)
+
+
+@pytest.mark.parametrize("impl", METHOD_IMPLS)
+@pytest.mark.parametrize("D", [1, 4, 8, 12])
+def test_paper_accuracy_workload(impl, D):
+    pins.pin_paper_accuracy(IMPLS[impl], D, exact_fn=oracle.naive if D > 10 else None)
+
+
+def test_table1_smallest_value_zero_error():
+    """Table 1 reports zero relative error of the method at z[(0,...,0)] = 1
+    for D = 11..18; the oracle reproduces that value exactly."""
+    g = pins.golden("table1_accuracy.json")
+    for D, err in zip(g["D"], g["dc_relative_error_at_smallest"]):
+        if D > 16:
+            continue  # the recursion at D = 17, 18 takes tens of seconds; the property is structural
+        x = np.arange(1, (1 << D) + 1, dtype=np.float64)
+        z = oracle.recursive(x, x.copy(), threads=8)
+        assert z[0] == g["smallest_value"]
+        assert abs(z[0] - 1.0) / 1.0 == err
+
+
+@pytest.mark.parametrize("impl", METHOD_IMPLS)
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("D,kind", [(2, "signed"), (4, "signed"), (5, "mass"), (6, "signed")])
+def test_exact_within_bound(impl, dtype, D, kind):
+    pins.pin_exact_bound(IMPLS[impl], dtype, D, oracle.bound, kind=kind)
+
+
+@pytest.mark.parametrize("impl", ["canonical", "recursive_mt"])
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("D", [0, 1, 2, 3, 6, 9, 12])
+def test_matches_recursion(impl, dtype, D):
+    pins.pin_matches_recursion(IMPLS[impl], dtype, D, oracle.recursive)
+
+
+@pytest.mark.parametrize("D", [7, 10])
+def test_direct_at_matches_definition(D):
+    """The per-index definition sum equals scipy's direct convolution (int64)
+    and is within a few long-double ulps of it for float64."""
+    g = np.random.default_rng([41, D])
+    x = g.integers(0, 16, 1 << D, dtype=np.int64)
+    y = g.integers(0, 16, 1 << D, dtype=np.int64)
+    ks = np.arange(3 ** D, dtype=np.uint64)
+    pins.assert_bitwise(oracle.direct_at(x, y, ks), pins.scipy_definition(x, y), "direct_at int64")
+    xf, yf = x.astype(np.float64), y.astype(np.float64)
+    assert np.array_equal(oracle.direct_at(xf, yf, ks), pins.scipy_definition(x, y).astype(np.float64))
+
+
+@pytest.mark.parametrize("D", [8, 10])
+def test_mass_inputs_within_bound_vs_direct(D):
+    """For the workloads' normalised masses the method stays within the
+    derived bound of the (compensated) definition at every output."""
+    g = np.random.default_rng([43, D])
+    x = g.random(1 << D); x /= x.sum()
+    y = g.random(1 << D); y /= y.sum()
+    z = oracle.canonical(x, y)
+    ref = oracle.direct_at(x, y, np.arange(3 ** D, dtype=np.uint64))
+    B = oracle.bound(x, y)
+    tol = (4 * D + 2) * 2.0 ** -53 * B + 2.0 ** -60 * np.abs(ref)  # + error of the compensated sum
+    assert np.all(np.abs(z - ref) <= tol)
+
+
+def test_tern_map():
+    g = pins.golden("carry_free_example.json")
+    assert oracle.tern(g["i"]) + oracle.tern(g["j"]) == g["k_flat"]
+    assert pins.ternary_digits(g["k_flat"], g["D"]) == g["k_digits_msb_first"]
+    t = oracle.tern_map(12)
+    assert all(int(t[i]) == pins.tern_py(i) for i in range(0, 4096, 7))
+
+
+# ----------------------------------------------------------------- adjoint pins
+
+def _loss(x, y, w):
+    return float(np.dot(w, oracle.canonical(x, y)))
+
+
+@pytest.mark.parametrize("D", [1, 3, 6, 9])
+def test_adjoint_vs_correlation(D):
+    """Transposed-map gradient vs the direct correlation (definition of the
+    gradient of sum(w * z)), within the derived adjoint bound."""
+    g = np.random.default_rng([47, D])
+    x = g.random(1 << D); x /= x.sum()
+    y = g.random(1 << D); y /= y.sum()
+    w = g.standard_normal(3 ** D)
+    gx, gy = oracle.adjoint(x, y, w)
+    idx = np.arange(1 << D, dtype=np.uint64)
+    cx, cy = oracle.correlation_at(x, y, w, idx)
+    bx, by = oracle.adjoint_bound(x, y, w)
+    tol = (4 * D + 2) * 2.0 ** -53
+    assert np.all(np.abs(gx - cx) <= tol * bx + 1e-300)
+    assert np.all(np.abs(gy - cy) <= tol * by + 1e-300)
+
+
+@pytest.mark.parametrize("D", [2, 5, 8])
+def test_adjoint_int_exact(D):
+    """int64: the adjoint equals the correlation written with the index map,
+    and L = <w, z(x, y)> = <gx, x> = <gy, y> exactly (bilinearity)."""
+    g = np.random.default_rng([53, D])
+    x = g.integers(-8, 8, 1 << D, dtype=np.int64)
+    y = g.integers(-8, 8, 1 << D, dtype=np.int64)
+    w = g.integers(-8, 8, 3 ** D, dtype=np.int64)
+    gx, gy = oracle.adjoint(x, y, w)
+    t = np.array([pins.tern_py(i) for i in range(1 << D)], dtype=np.int64)
+    W = w[t[:, None] + t[None, :]]          # W[i, j] = w[tern(i) + tern(j)]
+    pins.assert_bitwise(gx, W @ y, "gx correlation")
+    pins.assert_bitwise(gy, W.T @ x, "gy correlation")
+    L = int(np.dot(w, oracle.canonical(x, y)))
+    assert L == int(np.dot(gx, x)) == int(np.dot(gy, y))
+
+
+@pytest.mark.parametrize("D", [3, 7])
+def test_adjoint_finite_differences(D):
+    """Central differences with h = 1e-6 on L(x, y) = sum(w * z); L is
+    bilinear, so the difference has no truncation error, only rounding."""
+    g = np.random.default_rng([59, D])
+    x = g.random(1 << D); x /= x.sum()
+    y = g.random(1 << D); y /= y.sum()
+    w = g.standard_normal(3 ** D)
+    gx, gy = oracle.adjoint(x, y, w)
+    h = 1e-6
+    scale = max(np.abs(gx).max(), np.abs(gy).max())
+    for i in g.integers(0, 1 << D, 8):
+        e = np.zeros(1 << D); e[i] = h
+        fdx = (_loss(x + e, y, w) - _loss(x - e, y, w)) / (2 * h)
+        fdy = (_loss(x, y + e, w) - _loss(x, y - e, w)) / (2 * h)
+        assert abs(fdx - gx[i]) <= 1e-6 * scale
+        assert abs(fdy - gy[i]) <= 1e-6 * scale
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_adjoint_all_ones(dtype):
+    """x = y = w = 1: L = sum(z) = sum(x) sum(y), so every partial derivative
+    with respect to x[i] is sum(y) = 2^D, exactly in both precisions."""
+    D = 6
+    x = np.ones(1 << D, dtype=dtype)
+    w = np.ones(3 ** D, dtype=dtype)
+    gx, gy = oracle.adjoint(x, x.copy(), w)
+    assert np.all(gx == 2 ** D) and np.all(gy == 2 ** D)
