@@ -1,0 +1,251 @@
+#!/usr/bin/env python3
+"""Benchmark of exact hypercube convolution on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload d20]
+
+A step is one full pass of the method (outer forward, fused inner tiles,
+outer inverse passes) over the workload, with inputs already resident in HBM.
+Prints ONE JSON line: output elements per second for the workload, the
+roofline of the dominant kernel (algorithmic bytes per launch over its
+HIP-event-timed duration on the launch stream, against the 8 TB/s HBM peak),
+and the CPU oracle timed on a bounded sample of the same workload.
+
+Workloads (inputs from hc_inputs, seeded and synthetic):
+  d20       one pair, D=20, float64 masses              (default; 3^20 outputs)
+  d16-f64   one pair, D=16, float64 masses
+  d16-i64   one pair, D=16, int64 values in [0, 15]
+  d10       one pair, D=10, float64 masses
+  backward  64 pairs at D=16 float64, forward + backward of sum(w * z)
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "3^D output elems/sec + % HBM peak, D=20 fp64; batched pairs/s; fwd+bwd time"
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+PROFILES = os.path.join(ROOT, "profiles")
+TRAFFIC_FILE = os.path.join(PROFILES, "traffic.json")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1608_00206_amd", "csrc", f)
+                  for f in ("hc_device.hpp", "hc_kernels.hpp")]
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def measured_traffic(kernel: str, launches_per_step: float):
+    """HBM bytes per launch of `kernel` from committed rocprofv3 counter runs
+    (FETCH_SIZE and WRITE_SIZE, scaled by a copy-kernel calibration), or None
+    when none were taken on the current kernel source."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_sha") != kernel_source_hash():
+        return None
+    k = t.get("kernels", {}).get(kernel)
+    if not k:
+        return None
+    return (k["fetch_kib"] * t["fetch_scale"] + k["write_kib"] * t["write_scale"]) * 1024.0
+
+
+def time_steps(fn, steps: int, warmup: int, torch):
+    """Runs fn warmup times, then times exactly `steps` calls bracketed by
+    device synchronisation; the library profiler records every launch."""
+    from paper_1608_00206_amd import _abi
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    _abi.hc_profile_collect()  # drop anything recorded so far
+    _abi.hc_profile_enable(True)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record()
+    for _ in range(steps):
+        fn()
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    _abi.hc_profile_enable(False)
+    stats = _abi.hc_profile_collect()
+    return ev0.elapsed_time(ev1) / steps, wall, stats
+
+
+def roofline(stats, steps: int):
+    dom = max(stats, key=lambda s: s[2])
+    name, launches, total_ms, alg_bytes = dom
+    avg_s = total_ms / launches / 1e3
+    per_launch = alg_bytes / launches
+    achieved = per_launch / avg_s / 1e9
+    traffic = measured_traffic(name, launches / steps)
+    return {"bound": "hbm", "kernel": name, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": None if traffic is None else round(traffic),
+            "alg_bytes_per_launch": round(per_launch), "avg_launch_ms": round(avg_s * 1e3, 4)}
+
+
+def kernel_table(stats, steps):
+    out = []
+    for name, launches, total_ms, alg_bytes in sorted(stats, key=lambda s: -s[2]):
+        avg_ms = total_ms / launches
+        out.append({"kernel": name, "launches_per_step": launches / steps, "avg_ms": round(avg_ms, 4),
+                    "alg_GBps": round(alg_bytes / launches / (avg_ms / 1e3) / 1e9, 1)})
+    return out
+
+
+def cpu_baseline(x, y, z_gpu, D):
+    """The oracle (the three-subproblem recursion) timed on the workload
+    itself, on up to 16 host threads; the GPU output is then compared with
+    it bit for bit, chunk by chunk."""
+    import numpy as np
+
+    import oracle
+    threads = min(16, os.cpu_count() or 1)
+    out = np.empty(3 ** D, dtype=x.dtype)
+    log(f"cpu baseline: oracle recursion D={D} on {threads} threads")
+    t0 = time.perf_counter()
+    oracle.recursive(x, y, threads=threads, out=out)
+    dt = time.perf_counter() - t0
+    equal = True
+    chunk = 1 << 26
+    for s in range(0, out.size, chunk):
+        e = min(s + chunk, out.size)
+        g = z_gpu[s:e].cpu().numpy()
+        if not np.array_equal(g.view(np.int64), out[s:e].view(np.int64)):
+            equal = False
+            break
+    log(f"cpu baseline: {dt:.2f} s; GPU output bitwise equal: {equal}")
+    return {"value": round(3 ** D / dt, 1), "unit": "output elems/s", "cores": threads, "kind": "oracle",
+            "sample": f"the whole workload (one D={D} pair), three-subproblem recursion",
+            "seconds": round(dt, 3), "gpu_output_bitwise_equal": equal}
+
+
+def run_single(args, torch, hc, D, dtype_name):
+    import numpy as np
+
+    import hc_inputs
+    dev = torch.device("cuda:0")
+    if dtype_name == "i64":
+        x, y = hc_inputs.pair_ints(D, hc_inputs.W_D16)
+        tdt = torch.int64
+        desc = f"single pair D={D} int64, iid integers in [0,15] (seeded)"
+    else:
+        wl = {20: hc_inputs.W_D20_F64, 16: hc_inputs.W_D16, 10: hc_inputs.W_D10_F64}[D]
+        x, y = hc_inputs.pair_masses(D, wl)
+        tdt = torch.float64
+        desc = f"single pair D={D} float64, iid U[0,1) normalised to sum 1 (seeded)"
+    tx = torch.from_numpy(x).to(dev)
+    ty = torch.from_numpy(y).to(dev)
+    z = torch.empty(3 ** D, dtype=tdt, device=dev)
+    nb = hc.workspace_bytes(D, tdt)
+    ws = torch.empty(max(nb, 1), dtype=torch.uint8, device=dev)
+    log(f"workload {desc}: z {z.numel() * z.element_size() / 1e9:.2f} GB, workspace {nb / 1e9:.2f} GB")
+
+    def step():
+        hc.convolve(tx, ty, out=z, workspace=ws)
+
+    ms, wall, stats = time_steps(step, args.steps, args.warmup, torch)
+    log(f"timed {args.steps} steps: {ms:.3f} ms/step (wall {wall:.3f} s)")
+    n_out = 3 ** D
+    res = {
+        "metric": METRIC, "value": round(n_out / (ms / 1e3), 1), "unit": "output elems/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": dtype_name, "data": "synthetic",
+        "config": {"workload": desc, "D": D, "outputs_per_step": n_out, "global_batch": 1,
+                   "parallelism": "single GPU"},
+        "roofline": roofline(stats, args.steps),
+        "compulsory_hbm_frac": round((n_out + 2 * (1 << D)) * z.element_size() / (ms / 1e3) / 1e9
+                                     / HBM_PEAK_GBS, 4),
+        "kernels": kernel_table(stats, args.steps),
+    }
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(x, y, z, D)
+    return res
+
+
+def run_backward(args, torch, hc):
+    """64 pairs at D=16 float64, forward then backward of L = sum(w * z)."""
+    import numpy as np
+
+    import hc_inputs
+    dev = torch.device("cuda:0")
+    D, B = 16, 64
+    X = torch.from_numpy(np.stack([hc_inputs.pair_masses(D, hc_inputs.W_BACKWARD, b)[0] for b in range(B)])).to(dev)
+    Y = torch.from_numpy(np.stack([hc_inputs.pair_masses(D, hc_inputs.W_BACKWARD, b)[1] for b in range(B)])).to(dev)
+    W = torch.empty((B, 3 ** D), dtype=torch.float64, device=dev)
+    for b in range(B):
+        W[b].copy_(torch.from_numpy(hc_inputs.loss_weights(D, pair=b)))
+    Z = torch.empty((B, 3 ** D), dtype=torch.float64, device=dev)
+    wsf = torch.empty(max(hc.workspace_bytes(D, torch.float64, B), 1), dtype=torch.uint8, device=dev)
+    wsb = torch.empty(max(hc.backward_workspace_bytes(D, torch.float64, B), 1), dtype=torch.uint8, device=dev)
+    log(f"workload backward: {B} pairs D={D}; z and w {2 * Z.numel() * 8 / 1e9:.1f} GB")
+
+    def fwd():
+        hc.convolve_batch(X, Y, out=Z, workspace=wsf)
+
+    def bwd():
+        hc.convolve_backward(X, Y, W, workspace=wsb)
+
+    fwd_ms, _, fstats = time_steps(fwd, args.steps, args.warmup, torch)
+    bwd_ms, _, bstats = time_steps(bwd, args.steps, args.warmup, torch)
+    n_out = B * 3 ** D
+    return {
+        "metric": METRIC, "value": round(n_out / ((fwd_ms + bwd_ms) / 1e3), 1), "unit": "output elems/s (fwd+bwd)",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(fwd_ms + bwd_ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"{B} pairs D={D} float64 masses, loss sum(w*z), w iid N(0,1) per pair",
+                   "D": D, "global_batch": B, "parallelism": "single GPU"},
+        "fwd_ms": round(fwd_ms, 4), "bwd_ms": round(bwd_ms, 4),
+        "roofline": roofline(bstats, args.steps),
+        "kernels": kernel_table(fstats, args.steps) + kernel_table(bstats, args.steps),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="d20", choices=["d20", "d16-f64", "d16-i64", "d10", "backward"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build runs on one GPU only; --gpus must be 1 "
+              "(multi-GPU sharding is a design note, not implemented)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1608_00206_amd as hc
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    if args.workload == "backward":
+        res = run_backward(args, torch, hc)
+    else:
+        D = {"d20": 20, "d16-f64": 16, "d16-i64": 16, "d10": 10}[args.workload]
+        res = run_single(args, torch, hc, D, "i64" if args.workload == "d16-i64" else "f64")
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

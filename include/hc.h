@@ -1,0 +1,189 @@
+/*
+ * hc.h -- C ABI of libhc, exact convolution of hypercubes on AMD gfx950.
+ *
+ * The operation (Serang, "An exact, cache-localized algorithm for the
+ * sub-quadratic convolution of hypercubes"; Introduction, definition of
+ * tensor convolution, specialised to hypercubes {0,1}^D):
+ *
+ *     z[k] = sum over i, j in {0,1}^D with i + j = k of x[i] * y[j],
+ *
+ * where i + j adds the index vectors digit by digit, so every digit of k is
+ * 0, 1 or 2 and z has 3^D entries.  It is computed with the method of the
+ * Methods section (the three-subproblem recursion z[1] = t - z[0] - z[2],
+ * t the convolution of the marginals x[0] + x[1] and y[0] + y[1]) in its
+ * per-axis form:
+ *     forward  (a0, a1)     -> (a0, a0 + a1, a1)      on axes 0, 1, ..., D-1
+ *     product  elementwise
+ *     inverse  (p0, p1, p2) -> (p0, (p1 - p0) - p2, p2)  on axes D-1, ..., 1, 0
+ * Every floating-point operation is one IEEE operation in exactly this order
+ * (no contraction into fused multiply-adds, no reassociation), so results are
+ * bitwise reproducible and independent of tiling and tuning.  int64 data is
+ * computed in wrapping 64-bit arithmetic, which is exact whenever the true
+ * result fits in int64 (the method's identities hold in any ring).
+ *
+ * Memory layout (Methods section: tensors stored row-major):
+ *   x, y  2^D contiguous elements; bit d of the flat index (weight 2^d) is
+ *         the coordinate on axis D-1-d, so axis 0 is the most significant bit.
+ *   z     3^D contiguous elements; ternary digit d of the flat index (weight
+ *         3^d) is the coordinate on axis D-1-d.
+ *   x[i] * y[j] therefore contributes to z[tern(i) + tern(j)], tern(i) being
+ *   i's bits read as ternary digits (Discussion: carry-free convolution).
+ *
+ * Conventions for every entry point:
+ *   - Data pointers are DEVICE pointers (memory of the current HIP device);
+ *     the caller owns all buffers, including the workspace.  Nothing on the
+ *     hot path allocates; plans allocate their own small tables when created.
+ *   - Inputs are read-only (unlike the paper's listing, which overwrites x
+ *     and y).  Outputs must not overlap inputs or the workspace.
+ *   - All data and workspace pointers must be 16-byte aligned.
+ *   - Work is enqueued on `stream` (0 = the null stream); nothing synchronises.
+ *   - Argument errors are detected on the host before anything is enqueued.
+ *     Faults inside kernels surface asynchronously, as HC_ERR_HIP from a
+ *     later call or from the caller's own synchronisation.
+ *   - Return value: HC_OK or one of the hc_status codes below;
+ *     hc_last_error() gives a message for the calling thread's last failure.
+ */
+#ifndef HC_H
+#define HC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HC_ABI_VERSION 1
+/* Largest D accepted; 3^21 float64 outputs are 84 GB. */
+#define HC_MAX_D 21
+
+typedef enum hc_dtype {
+    HC_F64 = 0, /* IEEE binary64 */
+    HC_F32 = 1, /* IEEE binary32 */
+    HC_I64 = 2  /* two's complement int64, wrapping arithmetic */
+} hc_dtype;
+
+typedef enum hc_status {
+    HC_OK = 0,
+    HC_ERR_INVALID_ARG = 1, /* null pointer, bad count, bad flag */
+    HC_ERR_D_RANGE = 2,     /* D < 0 or D > HC_MAX_D */
+    HC_ERR_UNSUPPORTED = 3, /* dtype not supported by this entry point */
+    HC_ERR_ALIAS = 4,       /* an output overlaps an input or the workspace */
+    HC_ERR_MISALIGNED = 5,  /* a pointer is not 16-byte aligned */
+    HC_ERR_WORKSPACE = 6,   /* workspace missing or smaller than required */
+    HC_ERR_NO_DEVICE = 7,   /* no usable HIP device */
+    HC_ERR_HIP = 8          /* a HIP runtime call failed */
+} hc_status;
+
+/* ABI version of the loaded library (HC_ABI_VERSION at build time). */
+int hc_abi_version(void);
+
+/* Static message for a status code. */
+const char* hc_status_string(int status);
+
+/* Message describing the calling thread's most recent failure ("" if none). */
+const char* hc_last_error(void);
+
+/* Size in bytes of one element of `dtype`, or 0 if the dtype is unknown. */
+size_t hc_dtype_size(int dtype);
+
+/* Number of outputs 3^D (0 if D is out of range). */
+uint64_t hc_output_count(int D);
+
+/*
+ * Workspace for hc_convolve_batch (batch items of the same D), in bytes.
+ * It holds the outer-forward images of x and y (3^(D-K) x 2^K each per batch
+ * item, K the fused inner depth) and their staging.  Returns 0 when the
+ * whole problem fits one fused tile (then no workspace is needed), and
+ * (size_t)-1 for invalid arguments.
+ */
+size_t hc_workspace_bytes(int D, int dtype, int batch);
+
+/*
+ * Single convolution z = x * y of two D-dimensional hypercubes.
+ *   x, y        device, 2^D elements of `dtype` each (read only)
+ *   z           device, 3^D elements (written)
+ *   workspace   device, at least hc_workspace_bytes(D, dtype, 1) bytes
+ *               (may be NULL when that is 0)
+ * Errors: HC_ERR_INVALID_ARG (null x/y/z), HC_ERR_D_RANGE, HC_ERR_UNSUPPORTED
+ * (unknown dtype), HC_ERR_ALIAS (z overlaps x, y or workspace),
+ * HC_ERR_MISALIGNED, HC_ERR_WORKSPACE, HC_ERR_NO_DEVICE, HC_ERR_HIP.
+ */
+int hc_convolve(const void* x, const void* y, void* z, int D, int dtype,
+                void* workspace, size_t workspace_bytes, hipStream_t stream);
+
+/*
+ * `batch` independent convolutions of the same D:
+ *   z[b] = x[b] * y[b],  x[b] = x + b * 2^D elements, z[b] = z + b * 3^D.
+ * Same buffers, errors and workspace rules as hc_convolve with
+ * hc_workspace_bytes(D, dtype, batch).  1 <= batch <= 65535.
+ */
+int hc_convolve_batch(const void* x, const void* y, void* z, int D, int dtype, int batch,
+                      void* workspace, size_t workspace_bytes, hipStream_t stream);
+
+/*
+ * Workspace for hc_convolve_backward_batch, in bytes ((size_t)-1 if invalid).
+ */
+size_t hc_backward_workspace_bytes(int D, int dtype, int batch);
+
+/*
+ * Gradient of L = sum_b sum_k w[b][k] z[b][k] with z[b] = x[b] * y[b]:
+ *   grad_x[b][i] = sum_j w[b][tern(i) + tern(j)] * y[b][j]
+ *   grad_y[b][j] = sum_i w[b][tern(i) + tern(j)] * x[b][i]
+ * computed by the transposed maps in reverse order (derived: z is bilinear
+ * in x and y, so dL/dx = F^T (G^T w . F y)):
+ *   G^T: (w0, w1, w2) -> (w0 - w1, w1, w2 - w1)   on axes 0, 1, ..., D-1
+ *   F^T: (g0, g1, g2) -> (g0 + g1, g1 + g2)       on axes D-1, ..., 0
+ *   x, y          device, batch x 2^D (read only)
+ *   grad_z        device, 3^D elements per batch item at stride
+ *                 grad_z_stride elements; stride 0 broadcasts one w to every
+ *                 item (read only)
+ *   grad_x/grad_y device, batch x 2^D (written); either may be NULL
+ *   workspace     at least hc_backward_workspace_bytes(D, dtype, batch)
+ * Supported dtypes: HC_F64, HC_F32 (HC_I64 returns HC_ERR_UNSUPPORTED).
+ * Errors as hc_convolve; HC_ERR_INVALID_ARG also when both grads are NULL or
+ * grad_z_stride is neither 0 nor >= 3^D.
+ */
+int hc_convolve_backward_batch(const void* x, const void* y, const void* grad_z,
+                               int64_t grad_z_stride, void* grad_x, void* grad_y,
+                               int D, int dtype, int batch,
+                               void* workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* Single-pair form of hc_convolve_backward_batch (batch 1). */
+int hc_convolve_backward(const void* x, const void* y, const void* grad_z,
+                         void* grad_x, void* grad_y, int D, int dtype,
+                         void* workspace, size_t workspace_bytes, hipStream_t stream);
+
+/*
+ * Kernel profiler (measurement support; not part of the method).
+ * While enabled, every kernel launch of the calling process is bracketed by
+ * a pair of HIP events recorded on the launch stream, and tagged with the
+ * kernel's name and its algorithmic traffic (bytes the kernel must read and
+ * write by definition of its step, not counting re-reads).  Not to be used
+ * during stream capture.
+ */
+typedef struct hc_kernel_stat {
+    char name[48];       /* kernel and template configuration */
+    int64_t launches;    /* launches recorded */
+    double total_ms;     /* summed event-to-event time of those launches */
+    double alg_bytes;    /* summed algorithmic bytes of those launches */
+} hc_kernel_stat;
+
+/* Start (on != 0) or stop recording.  Returns HC_OK. */
+int hc_profile_enable(int on);
+
+/*
+ * Wait for every recorded event, aggregate by kernel name into `out`
+ * (at most `capacity` entries, *count receives the number written) and
+ * clear the record.  Errors: HC_ERR_INVALID_ARG (null count or out with
+ * capacity > 0), HC_ERR_HIP.
+ */
+int hc_profile_collect(hc_kernel_stat* out, int capacity, int* count);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HC_H */

@@ -1,0 +1,189 @@
+"""Exact convolution of hypercubes {0,1}^D on AMD MI355X (gfx950).
+
+Implements the sub-quadratic method of Serang's "An exact, cache-localized
+algorithm for the sub-quadratic convolution of hypercubes" (Methods section:
+three sub-convolutions per axis, z[1] = t - z[0] - z[2]) with hand-written
+HIP kernels behind the C ABI in ``include/hc.h``.  PyTorch only supplies
+device memory and the current stream; every step of the computation runs in
+libhc's kernels.
+
+    import torch, paper_1608_00206_amd as hc
+    x = torch.rand(2 ** 16, dtype=torch.float64, device="cuda")
+    y = torch.rand(2 ** 16, dtype=torch.float64, device="cuda")
+    z = hc.convolve(x, y)            # 3^16 outputs, row-major ternary index
+    z = hc.HypercubeConv.apply(x, y) # differentiable
+
+Layouts: x and y hold 2^D values whose flat index bits are the axes (axis 0
+the most significant bit); z holds 3^D values whose ternary digits are the
+axes.  Batches are (B, 2^D) -> (B, 3^D).
+"""
+from __future__ import annotations
+
+import torch
+
+from . import _abi
+from ._abi import HCError
+
+__all__ = ["convolve", "convolve_batch", "convolve_backward", "HypercubeConv", "HCError",
+           "workspace_bytes", "backward_workspace_bytes", "dim_of", "DTYPES"]
+
+DTYPES = {torch.float64: _abi.HC_F64, torch.float32: _abi.HC_F32, torch.int64: _abi.HC_I64}
+
+
+def dim_of(n: int) -> int:
+    D = int(n).bit_length() - 1
+    if n <= 0 or (1 << D) != n:
+        raise ValueError(f"a hypercube has 2^D entries, got {n}")
+    return D
+
+
+def _dtype_code(t: torch.Tensor) -> int:
+    try:
+        return DTYPES[t.dtype]
+    except KeyError:
+        raise TypeError(f"unsupported dtype {t.dtype}; use float64, float32 or int64") from None
+
+
+def _stream(device: torch.device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _check_device(*ts: torch.Tensor) -> None:
+    dev = ts[0].device
+    if dev.type != "cuda":
+        raise ValueError("tensors must be on a HIP device (device='cuda')")
+    for t in ts[1:]:
+        if t.device != dev:
+            raise ValueError("all tensors must be on the same device")
+
+
+def workspace_bytes(D: int, dtype: torch.dtype, batch: int = 1) -> int:
+    n = _abi.hc_workspace_bytes(D, DTYPES[dtype], batch)
+    if n == _abi.SIZE_MAX:
+        raise ValueError("invalid D, dtype or batch")
+    return n
+
+
+def backward_workspace_bytes(D: int, dtype: torch.dtype, batch: int = 1) -> int:
+    n = _abi.hc_backward_workspace_bytes(D, DTYPES[dtype], batch)
+    if n == _abi.SIZE_MAX:
+        raise ValueError("invalid D, dtype or batch")
+    return n
+
+
+def _workspace(nbytes: int, device, workspace):
+    if nbytes == 0:
+        return None
+    if workspace is not None:
+        if workspace.device != device or workspace.numel() * workspace.element_size() < nbytes:
+            raise ValueError(f"workspace needs {nbytes} bytes on {device}")
+        return workspace
+    return torch.empty(nbytes, dtype=torch.uint8, device=device)
+
+
+def convolve_batch(x: torch.Tensor, y: torch.Tensor, out: torch.Tensor | None = None,
+                   workspace: torch.Tensor | None = None) -> torch.Tensor:
+    """z[b] = x[b] * y[b] for x, y of shape (B, 2^D); returns (B, 3^D)."""
+    if x.dim() != 2 or x.shape != y.shape:
+        raise ValueError("x and y must both have shape (B, 2^D)")
+    if x.dtype != y.dtype:
+        raise TypeError("x and y must have the same dtype")
+    _check_device(x, y)
+    B, n = x.shape
+    D = dim_of(n)
+    code = _dtype_code(x)
+    x = x.contiguous()
+    y = y.contiguous()
+    if out is None:
+        out = torch.empty((B, 3 ** D), dtype=x.dtype, device=x.device)
+    elif out.shape != (B, 3 ** D) or out.dtype != x.dtype or not out.is_contiguous() or out.device != x.device:
+        raise ValueError("out must be a contiguous (B, 3^D) tensor of the input dtype")
+    nbytes = workspace_bytes(D, x.dtype, B)
+    ws = _workspace(nbytes, x.device, workspace)
+    _abi.check(_abi.hc_convolve_batch(x.data_ptr(), y.data_ptr(), out.data_ptr(), D, code, B,
+                                      ws.data_ptr() if ws is not None else 0, nbytes, _stream(x.device)))
+    return out
+
+
+def convolve(x: torch.Tensor, y: torch.Tensor, out: torch.Tensor | None = None,
+             workspace: torch.Tensor | None = None) -> torch.Tensor:
+    """z = x * y for one pair of hypercubes.
+
+    x, y: shape (2^D,) or (2,)*D.  Returns shape (3^D,) or (3,)*D to match.
+    """
+    if x.shape != y.shape:
+        raise ValueError("x and y must have the same shape")
+    n = x.numel()
+    D = dim_of(n)
+    if x.dim() >= 2 and any(s != 2 for s in x.shape):
+        raise ValueError("a multi-dimensional input must have shape (2,)*D")
+    flat_out = out.view(1, 3 ** D) if out is not None else None
+    z = convolve_batch(x.reshape(1, n), y.reshape(1, n), out=flat_out, workspace=workspace)
+    return z.view((3,) * D) if x.dim() >= 2 else z.view(3 ** D)
+
+
+def convolve_backward(x: torch.Tensor, y: torch.Tensor, grad_z: torch.Tensor, need_x: bool = True,
+                      need_y: bool = True, workspace: torch.Tensor | None = None):
+    """Gradients of sum(grad_z * z) with respect to x and y.
+
+    x, y: (B, 2^D); grad_z: (B, 3^D), or (3^D,) / an expanded (B, 3^D) view
+    with batch stride 0 to share one weight vector across the batch.
+    Returns (grad_x or None, grad_y or None).
+    """
+    if x.dim() != 2 or x.shape != y.shape:
+        raise ValueError("x and y must both have shape (B, 2^D)")
+    _check_device(x, y, grad_z)
+    B, n = x.shape
+    D = dim_of(n)
+    code = _dtype_code(x)
+    if grad_z.dtype != x.dtype:
+        raise TypeError("grad_z must have the dtype of x")
+    x = x.contiguous()
+    y = y.contiguous()
+    n3 = 3 ** D
+    if grad_z.dim() == 1:
+        if grad_z.numel() != n3:
+            raise ValueError("grad_z must have 3^D entries")
+        gz, gz_stride = grad_z.contiguous(), 0
+    else:
+        if grad_z.shape != (B, n3):
+            raise ValueError("grad_z must have shape (B, 3^D)")
+        if B > 1 and grad_z.stride(0) == 0 and grad_z.stride(1) == 1:
+            gz, gz_stride = grad_z, 0
+        else:
+            gz = grad_z.contiguous()
+            gz_stride = n3
+    gx = torch.empty_like(x) if need_x else None
+    gy = torch.empty_like(y) if need_y else None
+    nbytes = backward_workspace_bytes(D, x.dtype, B)
+    ws = _workspace(nbytes, x.device, workspace)
+    _abi.check(_abi.hc_convolve_backward_batch(
+        x.data_ptr(), y.data_ptr(), gz.data_ptr(), gz_stride,
+        gx.data_ptr() if gx is not None else 0, gy.data_ptr() if gy is not None else 0,
+        D, code, B, ws.data_ptr() if ws is not None else 0, nbytes, _stream(x.device)))
+    return gx, gy
+
+
+class HypercubeConv(torch.autograd.Function):
+    """Differentiable z = x * y.  Accepts (2^D,) or (B, 2^D) inputs; saves
+    only x and y (the forward transforms are recomputed in the backward)."""
+
+    @staticmethod
+    def forward(ctx, x, y):
+        ctx.save_for_backward(x, y)
+        if x.dim() == 1:
+            return convolve_batch(x.unsqueeze(0), y.unsqueeze(0)).squeeze(0)
+        return convolve_batch(x, y)
+
+    @staticmethod
+    def backward(ctx, grad_z):
+        x, y = ctx.saved_tensors
+        single = x.dim() == 1
+        if single:
+            x, y, grad_z = x.unsqueeze(0), y.unsqueeze(0), grad_z.unsqueeze(0)
+        gx, gy = convolve_backward(x, y, grad_z, need_x=ctx.needs_input_grad[0],
+                                   need_y=ctx.needs_input_grad[1])
+        if single:
+            gx = gx.squeeze(0) if gx is not None else None
+            gy = gy.squeeze(0) if gy is not None else None
+        return gx, gy

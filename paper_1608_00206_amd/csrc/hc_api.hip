@@ -1,0 +1,833 @@
+// Host side of libhc: argument validation, planning (fused depth, axis
+// groups), workspace layout and kernel launches.  See include/hc.h for the
+// contract of every entry point.
+#include "hc.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <type_traits>
+#include <vector>
+
+#include "hc_internal.hpp"
+#include "hc_kernels.hpp"
+
+namespace hc {
+
+// ------------------------------------------------------------------ errors
+static thread_local std::string g_last_error;
+
+int fail(int code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what)
+{
+    return fail(HC_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+uint64_t pow3u(int n)
+{
+    uint64_t r = 1;
+    for (int i = 0; i < n; ++i) r *= 3;
+    return r;
+}
+
+size_t dtype_size(int dtype)
+{
+    switch (dtype) {
+        case HC_F64: return 8;
+        case HC_F32: return 4;
+        case HC_I64: return 8;
+        default: return 0;
+    }
+}
+
+bool ranges_overlap(const void* a, size_t na, const void* b, size_t nb)
+{
+    if (!a || !b || na == 0 || nb == 0) return false;
+    const uintptr_t a0 = (uintptr_t)a, b0 = (uintptr_t)b;
+    return a0 < b0 + nb && b0 < a0 + na;
+}
+
+bool misaligned(const void* p)
+{
+    return p && ((uintptr_t)p & 15u) != 0;
+}
+
+// ------------------------------------------------------------------ device
+static std::mutex g_dev_mu;
+static int g_cu_count[64];
+
+int device_cus(int* cus)
+{
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess || n <= 0) {
+        (void)hipGetLastError();
+        return fail(HC_ERR_NO_DEVICE, "no HIP device available");
+    }
+    int dev = 0;
+    e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    std::lock_guard<std::mutex> lk(g_dev_mu);
+    if (dev < 0 || dev >= 64) return fail(HC_ERR_NO_DEVICE, "device index %d unsupported", dev);
+    if (g_cu_count[dev] == 0) {
+        int v = 0;
+        e = hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute");
+        g_cu_count[dev] = v > 0 ? v : 1;
+    }
+    *cus = g_cu_count[dev];
+    return HC_OK;
+}
+
+
+// ---------------------------------------------------------------- profiler
+// While enabled, each launch is bracketed by two events on its stream and
+// tagged with a name and its algorithmic bytes.
+struct ProfRec {
+    char name[48];
+    double bytes;
+    hipEvent_t a, b;
+};
+static std::mutex g_prof_mu;
+static bool g_prof_on = false;
+static std::vector<ProfRec> g_prof;
+static std::vector<hipEvent_t> g_event_pool;
+
+static hipEvent_t pooled_event()
+{
+    if (!g_event_pool.empty()) {
+        hipEvent_t e = g_event_pool.back();
+        g_event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+template <typename T>
+const char* tname()
+{
+    return sizeof(T) == 4 ? "f32" : (std::is_same<T, double>::value ? "f64" : "i64");
+}
+
+LaunchScope::LaunchScope(hipStream_t s, double bytes, const char* fmt, ...) : stream_(s), on_(false), idx_(0)
+{
+    if (!g_prof_on) return;
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    if (!g_prof_on) return;
+    ProfRec r;
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(r.name, sizeof(r.name), fmt, ap);
+    va_end(ap);
+    r.bytes = bytes;
+    r.a = pooled_event();
+    r.b = pooled_event();
+    if (!r.a || !r.b) return;
+    if (hipEventRecord(r.a, s) != hipSuccess) return;
+    g_prof.push_back(r);
+    idx_ = g_prof.size() - 1;
+    on_ = true;
+}
+
+LaunchScope::~LaunchScope()
+{
+    if (!on_) return;
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    if (idx_ < g_prof.size()) (void)hipEventRecord(g_prof[idx_].b, stream_);
+}
+
+// ------------------------------------------------------------------ plans
+int max_fused_depth(int dtype)
+{
+    // One fused tile of 3^K elements must fit LDS with room for two or more
+    // workgroups per CU: 3^8 x 8 B = 52.5 KB, 3^9 x 4 B = 78.7 KB.
+    return dtype_size(dtype) == 4 ? 9 : 8;
+}
+
+Plan make_plan(int D, int dtype, const PlanOpts& o)
+{
+    Plan P;
+    P.D = D;
+    P.dtype = dtype;
+    P.esize = dtype_size(dtype);
+    // the adjoint tile also keeps x and y in LDS beside w_hat: at most 8 axes
+    const int kmax = o.backward ? cmin(8, max_fused_depth(dtype)) : max_fused_depth(dtype);
+    int K = o.fused_depth > 0 ? o.fused_depth : kmax;
+    if (K > kmax) K = kmax;
+    if (K > D) K = D;
+    P.K = K;
+    P.p = D - K;
+    P.n2 = 1ull << D;
+    P.n3 = pow3u(D);
+    // outer forward groups (ascending), at most 4 axes each, balanced
+    if (P.p > 0) {
+        const int n = (P.p + 3) / 4;
+        int left = P.p;
+        for (int i = 0; i < n; ++i) {
+            const int m = (left + (n - i) - 1) / (n - i);
+            P.k1.push_back(m);
+            left -= m;
+        }
+    }
+    // outer inverse passes (descending), groups of at most max_m axes
+    const int max_m = o.inv_group_max > 0 ? o.inv_group_max : 6;
+    int top = P.p;  // axes [0, top) still to invert
+    while (top > 0) {
+        const int m = top < max_m ? top : max_m;
+        const int a = top - m;
+        InvPass ip;
+        ip.a = a;
+        if (m <= 4 && (o.inv_reg_only || m <= o.inv_reg_max)) {
+            ip.mA = m;
+            ip.mB = 0;
+        } else {
+            ip.mA = 3;
+            ip.mB = m - 3;
+            if (ip.mB > 3) { ip.mA = m - 3; ip.mB = 3; }
+        }
+        ip.C = o.inv_cols > 0 ? o.inv_cols : 16;
+        P.inv.push_back(ip);
+        top = a;
+    }
+    // workspace: K1 stages ping-pong between the x~ region and a staging region
+    P.xt_elems = P.p > 0 ? pow3u(P.p) << K : 0;
+    P.tmp_elems = 0;
+    {
+        const int n = (int)P.k1.size();
+        int a = 0;
+        for (int i = 0; i < n; ++i) {
+            a += P.k1[i];
+            const uint64_t e = pow3u(a) << (D - a);
+            if (((n - 1 - i) & 1) == 1 && e > P.tmp_elems) P.tmp_elems = e;
+        }
+    }
+    return P;
+}
+
+PlanOpts default_opts(bool backward)
+{
+    PlanOpts o;
+    o.backward = backward;
+    if (const char* s = getenv("HC_FUSED_K")) o.fused_depth = atoi(s);
+    if (const char* s = getenv("HC_INV_MAXM")) o.inv_group_max = atoi(s);
+    if (const char* s = getenv("HC_INV_COLS")) o.inv_cols = atoi(s);
+    if (const char* s = getenv("HC_INV_REG")) o.inv_reg_only = atoi(s) != 0;
+    return o;
+}
+
+size_t plan_ws_bytes(const Plan& P, int batch)
+{
+    if (P.p == 0) return 0;
+    return (size_t)batch * 2 * (P.xt_elems + P.tmp_elems) * P.esize;
+}
+
+// Backward workspace per item: W (3^D), x~, y~ and staging, gx~, gy~ and the
+// F^T staging (largest intermediate after the first F^T group).
+size_t plan_bwd_ws_elems(const Plan& P, uint64_t* w_e, uint64_t* gtmp_e)
+{
+    *w_e = P.p > 0 ? P.n3 : 0;
+    *gtmp_e = 0;
+    if (P.p > 0 && P.k1.size() > 1) {
+        // F^T groups run in the reverse order of the forward groups
+        const int m_last = P.k1.back();
+        const int a = P.p - m_last;
+        *gtmp_e = pow3u(a) << (P.D - a);
+    }
+    return 0;
+}
+
+size_t plan_bwd_ws_bytes(const Plan& P, int batch)
+{
+    if (P.p == 0) return 0;
+    uint64_t w_e, g_e;
+    plan_bwd_ws_elems(P, &w_e, &g_e);
+    const uint64_t per = w_e + 2 * (P.xt_elems + P.tmp_elems) + 2 * (P.xt_elems + g_e);
+    return (size_t)batch * per * P.esize;
+}
+
+// ------------------------------------------------------------- launches
+template <typename T, int M>
+static void launch_fwd_pass_m(const T* in0, const T* in1, T* out0, T* out1, uint64_t in_bs, uint64_t out_bs,
+                              uint32_t n_cols, uint32_t log2L, int batch, int ops, hipStream_t s)
+{
+    constexpr int NT = 256;
+    dim3 grid((n_cols + NT - 1) / NT, batch, ops);
+    const double bytes = (double)ops * batch * n_cols * ((1 << M) + pow3c(M)) * sizeof(T);
+    LaunchScope scope(s, bytes, "fwd_pass<%s,M=%d>", tname<T>(), M);
+    k_fwd_pass<T, M, NT><<<grid, NT, 0, s>>>(in0, in1, out0, out1, in_bs, out_bs, n_cols, log2L);
+}
+
+template <typename T>
+int launch_fwd_pass(int M, const T* in0, const T* in1, T* out0, T* out1, uint64_t in_bs, uint64_t out_bs,
+                     uint32_t n_cols, uint32_t log2L, int batch, int ops, hipStream_t s)
+{
+    switch (M) {
+        case 1: launch_fwd_pass_m<T, 1>(in0, in1, out0, out1, in_bs, out_bs, n_cols, log2L, batch, ops, s); break;
+        case 2: launch_fwd_pass_m<T, 2>(in0, in1, out0, out1, in_bs, out_bs, n_cols, log2L, batch, ops, s); break;
+        case 3: launch_fwd_pass_m<T, 3>(in0, in1, out0, out1, in_bs, out_bs, n_cols, log2L, batch, ops, s); break;
+        case 4: launch_fwd_pass_m<T, 4>(in0, in1, out0, out1, in_bs, out_bs, n_cols, log2L, batch, ops, s); break;
+        default: return fail(HC_ERR_UNSUPPORTED, "no forward pass for %d axes", M);
+    }
+    return HC_OK;
+}
+
+template <typename T, int M>
+static void launch_fwd_adj_pass_m(const T* in0, const T* in1, T* out0, T* out1, uint64_t in_bs, uint64_t out_bs,
+                                  uint32_t n_cols, uint32_t log2L, int batch, hipStream_t s)
+{
+    constexpr int NT = 256;
+    dim3 grid((n_cols + NT - 1) / NT, batch, 2);
+    const int ops = (out0 ? 1 : 0) + (out1 ? 1 : 0);
+    const double bytes = (double)ops * batch * n_cols * ((1 << M) + pow3c(M)) * sizeof(T);
+    LaunchScope scope(s, bytes, "fwd_adj_pass<%s,M=%d>", tname<T>(), M);
+    k_fwd_adj_pass<T, M, NT><<<grid, NT, 0, s>>>(in0, in1, out0, out1, in_bs, out_bs, n_cols, log2L);
+}
+
+template <typename T>
+int launch_fwd_adj_pass(int M, const T* in0, const T* in1, T* out0, T* out1, uint64_t in_bs, uint64_t out_bs,
+                         uint32_t n_cols, uint32_t log2L, int batch, hipStream_t s)
+{
+    switch (M) {
+        case 1: launch_fwd_adj_pass_m<T, 1>(in0, in1, out0, out1, in_bs, out_bs, n_cols, log2L, batch, s); break;
+        case 2: launch_fwd_adj_pass_m<T, 2>(in0, in1, out0, out1, in_bs, out_bs, n_cols, log2L, batch, s); break;
+        case 3: launch_fwd_adj_pass_m<T, 3>(in0, in1, out0, out1, in_bs, out_bs, n_cols, log2L, batch, s); break;
+        case 4: launch_fwd_adj_pass_m<T, 4>(in0, in1, out0, out1, in_bs, out_bs, n_cols, log2L, batch, s); break;
+        default: return fail(HC_ERR_UNSUPPORTED, "no adjoint forward pass for %d axes", M);
+    }
+    return HC_OK;
+}
+
+static uint32_t tile_grid(uint64_t n_tiles, int cus, int per_cu)
+{
+    uint64_t cap = (uint64_t)cus * per_cu;
+    uint64_t g = n_tiles < cap ? n_tiles : cap;
+    if (g >= 8) g &= ~7ull;
+    return (uint32_t)(g ? g : 1);
+}
+
+template <typename T, int K>
+static void launch_fused_k(const T* xt, const T* yt, T* z, uint64_t in_bs, uint64_t z_bs, uint32_t n_tiles,
+                           int batch, int cus, hipStream_t s)
+{
+    constexpr int NT = 256;
+    dim3 grid(tile_grid(n_tiles, cus, 16), batch, 1);
+    const double bytes = (double)batch * n_tiles * (2.0 * (1 << K) + pow3c(K)) * sizeof(T);
+    LaunchScope scope(s, bytes, "fused_inner<%s,K=%d>", tname<T>(), K);
+    k_fused_inner<T, K, NT><<<grid, NT, 0, s>>>(xt, yt, z, in_bs, z_bs, n_tiles);
+}
+
+template <typename T>
+int launch_fused(int K, const T* xt, const T* yt, T* z, uint64_t in_bs, uint64_t z_bs, uint32_t n_tiles,
+                  int batch, int cus, hipStream_t s)
+{
+    switch (K) {
+        case 0: launch_fused_k<T, 0>(xt, yt, z, in_bs, z_bs, n_tiles, batch, cus, s); break;
+        case 1: launch_fused_k<T, 1>(xt, yt, z, in_bs, z_bs, n_tiles, batch, cus, s); break;
+        case 2: launch_fused_k<T, 2>(xt, yt, z, in_bs, z_bs, n_tiles, batch, cus, s); break;
+        case 3: launch_fused_k<T, 3>(xt, yt, z, in_bs, z_bs, n_tiles, batch, cus, s); break;
+        case 4: launch_fused_k<T, 4>(xt, yt, z, in_bs, z_bs, n_tiles, batch, cus, s); break;
+        case 5: launch_fused_k<T, 5>(xt, yt, z, in_bs, z_bs, n_tiles, batch, cus, s); break;
+        case 6: launch_fused_k<T, 6>(xt, yt, z, in_bs, z_bs, n_tiles, batch, cus, s); break;
+        case 7: launch_fused_k<T, 7>(xt, yt, z, in_bs, z_bs, n_tiles, batch, cus, s); break;
+        case 8: launch_fused_k<T, 8>(xt, yt, z, in_bs, z_bs, n_tiles, batch, cus, s); break;
+        case 9:
+            if constexpr (sizeof(T) == 4) {
+                launch_fused_k<T, 9>(xt, yt, z, in_bs, z_bs, n_tiles, batch, cus, s);
+                break;
+            }
+            return fail(HC_ERR_UNSUPPORTED, "no fused tile of 9 axes for 8-byte elements");
+        default: return fail(HC_ERR_UNSUPPORTED, "no fused tile of %d axes", K);
+    }
+    return HC_OK;
+}
+
+template <typename T, int K>
+static void launch_fused_adj_k(const T* xt, const T* yt, const T* w, T* gxt, T* gyt, uint64_t in_bs,
+                               uint64_t w_bs, uint64_t g_bs, uint32_t n_tiles, int batch, int cus, hipStream_t s)
+{
+    constexpr int NT = 256;
+    dim3 grid(tile_grid(n_tiles, cus, 16), batch, 1);
+    const int ops = (gxt ? 1 : 0) + (gyt ? 1 : 0);
+    const double bytes = (double)batch * n_tiles * ((2.0 + ops) * (1 << K) + pow3c(K)) * sizeof(T);
+    LaunchScope scope(s, bytes, "fused_inner_adj<%s,K=%d>", tname<T>(), K);
+    k_fused_inner_adj<T, K, NT><<<grid, NT, 0, s>>>(xt, yt, w, gxt, gyt, in_bs, w_bs, g_bs, n_tiles);
+}
+
+template <typename T>
+int launch_fused_adj(int K, const T* xt, const T* yt, const T* w, T* gxt, T* gyt, uint64_t in_bs,
+                      uint64_t w_bs, uint64_t g_bs, uint32_t n_tiles, int batch, int cus, hipStream_t s)
+{
+    switch (K) {
+        case 0: launch_fused_adj_k<T, 0>(xt, yt, w, gxt, gyt, in_bs, w_bs, g_bs, n_tiles, batch, cus, s); break;
+        case 1: launch_fused_adj_k<T, 1>(xt, yt, w, gxt, gyt, in_bs, w_bs, g_bs, n_tiles, batch, cus, s); break;
+        case 2: launch_fused_adj_k<T, 2>(xt, yt, w, gxt, gyt, in_bs, w_bs, g_bs, n_tiles, batch, cus, s); break;
+        case 3: launch_fused_adj_k<T, 3>(xt, yt, w, gxt, gyt, in_bs, w_bs, g_bs, n_tiles, batch, cus, s); break;
+        case 4: launch_fused_adj_k<T, 4>(xt, yt, w, gxt, gyt, in_bs, w_bs, g_bs, n_tiles, batch, cus, s); break;
+        case 5: launch_fused_adj_k<T, 5>(xt, yt, w, gxt, gyt, in_bs, w_bs, g_bs, n_tiles, batch, cus, s); break;
+        case 6: launch_fused_adj_k<T, 6>(xt, yt, w, gxt, gyt, in_bs, w_bs, g_bs, n_tiles, batch, cus, s); break;
+        case 7: launch_fused_adj_k<T, 7>(xt, yt, w, gxt, gyt, in_bs, w_bs, g_bs, n_tiles, batch, cus, s); break;
+        case 8: launch_fused_adj_k<T, 8>(xt, yt, w, gxt, gyt, in_bs, w_bs, g_bs, n_tiles, batch, cus, s); break;
+        default: return fail(HC_ERR_UNSUPPORTED, "no adjoint fused tile of %d axes", K);
+    }
+    return HC_OK;
+}
+
+template <typename T, int mA, int mB, int C, int NT>
+static void launch_inv_pass_v(T* z, uint64_t z_bs, uint64_t L, uint32_t n_hi, int batch, int cus, hipStream_t s)
+{
+    const uint32_t cols = mB == 0 ? NT : C;
+    const uint32_t tiles_per_hi = (uint32_t)((L + cols - 1) / cols);
+    const uint64_t n_tiles = (uint64_t)tiles_per_hi * n_hi;
+    dim3 grid(tile_grid(n_tiles, cus, 16), batch, 1);
+    // reads every entry; writes those with a 1 among the group digits
+    const double n_all = (double)batch * n_hi * L;
+    const double bytes = n_all * (pow3c(mA + mB) + (pow3c(mA + mB) - (1 << (mA + mB)))) * sizeof(T);
+    LaunchScope scope(s, bytes, "inv_pass<%s,%d+%d,C=%d>", tname<T>(), mB, mA, mB ? C : NT);
+    k_inv_pass<T, mA, mB, C, NT><<<grid, NT, 0, s>>>(z, z_bs, L, tiles_per_hi, (uint32_t)n_tiles);
+}
+
+template <typename T>
+int launch_inv_pass(const InvPass& ip, T* z, uint64_t z_bs, uint64_t L, uint32_t n_hi, int batch, int cus,
+                    hipStream_t s)
+{
+    const int key = ip.mA * 100 + ip.mB * 10;
+    if (ip.mB == 0) {
+        switch (ip.mA) {
+            case 1: launch_inv_pass_v<T, 1, 0, 1, 256>(z, z_bs, L, n_hi, batch, cus, s); return HC_OK;
+            case 2: launch_inv_pass_v<T, 2, 0, 1, 256>(z, z_bs, L, n_hi, batch, cus, s); return HC_OK;
+            case 3: launch_inv_pass_v<T, 3, 0, 1, 256>(z, z_bs, L, n_hi, batch, cus, s); return HC_OK;
+            case 4: launch_inv_pass_v<T, 4, 0, 1, 256>(z, z_bs, L, n_hi, batch, cus, s); return HC_OK;
+            default: break;
+        }
+    } else if (ip.C == 16) {
+        switch (key) {
+            case 310: launch_inv_pass_v<T, 3, 1, 16, 448>(z, z_bs, L, n_hi, batch, cus, s); return HC_OK;
+            case 320: launch_inv_pass_v<T, 3, 2, 16, 448>(z, z_bs, L, n_hi, batch, cus, s); return HC_OK;
+            case 330: launch_inv_pass_v<T, 3, 3, 16, 448>(z, z_bs, L, n_hi, batch, cus, s); return HC_OK;
+            default: break;
+        }
+    } else if (ip.C == 8) {
+        switch (key) {
+            case 310: launch_inv_pass_v<T, 3, 1, 8, 256>(z, z_bs, L, n_hi, batch, cus, s); return HC_OK;
+            case 320: launch_inv_pass_v<T, 3, 2, 8, 256>(z, z_bs, L, n_hi, batch, cus, s); return HC_OK;
+            case 330: launch_inv_pass_v<T, 3, 3, 8, 256>(z, z_bs, L, n_hi, batch, cus, s); return HC_OK;
+            default: break;
+        }
+    }
+    return fail(HC_ERR_UNSUPPORTED, "no inverse-pass variant for groups (%d, %d) with %d columns", ip.mA, ip.mB,
+                ip.C);
+}
+
+template <typename T, int mA, int mB, int C, int NT>
+static void launch_inv_adj_pass_v(const T* src, T* dst, uint64_t src_bs, uint64_t dst_bs, uint64_t L,
+                                  uint32_t n_hi, int batch, int cus, hipStream_t s)
+{
+    const uint32_t cols = mB == 0 ? NT : C;
+    const uint32_t tiles_per_hi = (uint32_t)((L + cols - 1) / cols);
+    const uint64_t n_tiles = (uint64_t)tiles_per_hi * n_hi;
+    dim3 grid(tile_grid(n_tiles, cus, 16), batch, 1);
+    const double n_all = (double)batch * n_hi * L;
+    const double writes = src == dst ? (pow3c(mA + mB) - 1) : pow3c(mA + mB);
+    const double bytes = n_all * (pow3c(mA + mB) + writes) * sizeof(T);
+    LaunchScope scope(s, bytes, "inv_adj_pass<%s,%d+%d,C=%d>", tname<T>(), mB, mA, mB ? C : NT);
+    k_inv_adj_pass<T, mA, mB, C, NT><<<grid, NT, 0, s>>>(src, dst, src_bs, dst_bs, L, tiles_per_hi,
+                                                         (uint32_t)n_tiles);
+}
+
+template <typename T>
+int launch_inv_adj_pass(const InvPass& ip, const T* src, T* dst, uint64_t src_bs, uint64_t dst_bs, uint64_t L,
+                        uint32_t n_hi, int batch, int cus, hipStream_t s)
+{
+    const int key = ip.mA * 100 + ip.mB * 10;
+    if (ip.mB == 0) {
+        switch (ip.mA) {
+            case 1: launch_inv_adj_pass_v<T, 1, 0, 1, 256>(src, dst, src_bs, dst_bs, L, n_hi, batch, cus, s); return HC_OK;
+            case 2: launch_inv_adj_pass_v<T, 2, 0, 1, 256>(src, dst, src_bs, dst_bs, L, n_hi, batch, cus, s); return HC_OK;
+            case 3: launch_inv_adj_pass_v<T, 3, 0, 1, 256>(src, dst, src_bs, dst_bs, L, n_hi, batch, cus, s); return HC_OK;
+            case 4: launch_inv_adj_pass_v<T, 4, 0, 1, 256>(src, dst, src_bs, dst_bs, L, n_hi, batch, cus, s); return HC_OK;
+            default: break;
+        }
+    } else {
+        switch (key) {
+            case 310: launch_inv_adj_pass_v<T, 3, 1, 16, 448>(src, dst, src_bs, dst_bs, L, n_hi, batch, cus, s); return HC_OK;
+            case 320: launch_inv_adj_pass_v<T, 3, 2, 16, 448>(src, dst, src_bs, dst_bs, L, n_hi, batch, cus, s); return HC_OK;
+            case 330: launch_inv_adj_pass_v<T, 3, 3, 16, 448>(src, dst, src_bs, dst_bs, L, n_hi, batch, cus, s); return HC_OK;
+            default: break;
+        }
+    }
+    return fail(HC_ERR_UNSUPPORTED, "no adjoint inverse-pass variant for groups (%d, %d)", ip.mA, ip.mB);
+}
+
+// ------------------------------------------------------------ forward run
+template <typename T>
+int run_forward(const Plan& P, const T* x, const T* y, T* z, int batch, T* ws, int cus, hipStream_t s)
+{
+    const int D = P.D, K = P.K;
+    int rc = HC_OK;
+    if (P.p == 0) {
+        rc = launch_fused<T>(K, x, y, z, P.n2, P.n3, 1, batch, cus, s);
+        if (rc != HC_OK) return rc;
+    } else {
+        T* xt = ws;
+        T* yt = xt + (uint64_t)batch * P.xt_elems;
+        T* xtmp = yt + (uint64_t)batch * P.xt_elems;
+        T* ytmp = xtmp + (uint64_t)batch * P.tmp_elems;
+        // outer forward, ascending groups; the last group lands in x~ / y~
+        const int n = (int)P.k1.size();
+        const T* cx = x;
+        const T* cy = y;
+        uint64_t c_bs = P.n2;
+        int a = 0;
+        for (int i = 0; i < n; ++i) {
+            const int M = P.k1[i];
+            const bool to_xt = ((n - 1 - i) & 1) == 0;
+            T* ox = to_xt ? xt : xtmp;
+            T* oy = to_xt ? yt : ytmp;
+            const uint64_t o_bs = to_xt ? P.xt_elems : P.tmp_elems;
+            const int log2L = D - a - M;
+            const uint64_t n_cols = pow3u(a) << log2L;
+            rc = launch_fwd_pass<T>(M, cx, cy, ox, oy, c_bs, o_bs, (uint32_t)n_cols, (uint32_t)log2L, batch, 2, s);
+            if (rc != HC_OK) return rc;
+            cx = ox;
+            cy = oy;
+            c_bs = o_bs;
+            a += M;
+        }
+        rc = launch_fused<T>(K, xt, yt, z, P.xt_elems, P.n3, (uint32_t)pow3u(P.p), batch, cus, s);
+        if (rc != HC_OK) return rc;
+        for (const InvPass& ip : P.inv) {
+            const int m = ip.mA + ip.mB;
+            const uint64_t L = pow3u(D - ip.a - m);
+            const uint32_t n_hi = (uint32_t)pow3u(ip.a);
+            rc = launch_inv_pass<T>(ip, z, P.n3, L, n_hi, batch, cus, s);
+            if (rc != HC_OK) return rc;
+        }
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    return HC_OK;
+}
+
+// ----------------------------------------------------------- backward run
+template <typename T>
+int run_backward(const Plan& P, const T* x, const T* y, const T* gz, uint64_t gz_bs, T* gx, T* gy, int batch,
+                 T* ws, int cus, hipStream_t s)
+{
+    const int D = P.D, K = P.K;
+    int rc = HC_OK;
+    if (P.p == 0) {
+        rc = launch_fused_adj<T>(K, x, y, gz, gx, gy, P.n2, gz_bs, P.n2, 1, batch, cus, s);
+        if (rc != HC_OK) return rc;
+    } else {
+        uint64_t w_e, g_e;
+        plan_bwd_ws_elems(P, &w_e, &g_e);
+        T* W = ws;
+        T* xt = W + (uint64_t)batch * w_e;
+        T* yt = xt + (uint64_t)batch * P.xt_elems;
+        T* xtmp = yt + (uint64_t)batch * P.xt_elems;
+        T* ytmp = xtmp + (uint64_t)batch * P.tmp_elems;
+        T* gxt = ytmp + (uint64_t)batch * P.tmp_elems;
+        T* gyt = gxt + (uint64_t)batch * P.xt_elems;
+        T* gxtmp = gyt + (uint64_t)batch * P.xt_elems;
+        T* gytmp = gxtmp + (uint64_t)batch * g_e;
+        // 1. G^T on the outer axes, ascending; the first pass reads grad_z
+        const T* src = gz;
+        uint64_t src_bs = gz_bs;
+        for (int i = (int)P.inv.size() - 1; i >= 0; --i) {
+            const InvPass& ip = P.inv[i];
+            const int m = ip.mA + ip.mB;
+            const uint64_t L = pow3u(D - ip.a - m);
+            const uint32_t n_hi = (uint32_t)pow3u(ip.a);
+            rc = launch_inv_adj_pass<T>(ip, src, W, src_bs, P.n3, L, n_hi, batch, cus, s);
+            if (rc != HC_OK) return rc;
+            src = W;
+            src_bs = P.n3;
+        }
+        // 2. outer forward of x and y (recomputed, as in the forward)
+        const int n = (int)P.k1.size();
+        const T* cx = x;
+        const T* cy = y;
+        uint64_t c_bs = P.n2;
+        int a = 0;
+        for (int i = 0; i < n; ++i) {
+            const int M = P.k1[i];
+            const bool to_xt = ((n - 1 - i) & 1) == 0;
+            T* ox = to_xt ? xt : xtmp;
+            T* oy = to_xt ? yt : ytmp;
+            const uint64_t o_bs = to_xt ? P.xt_elems : P.tmp_elems;
+            const int log2L = D - a - M;
+            const uint64_t n_cols = pow3u(a) << log2L;
+            rc = launch_fwd_pass<T>(M, cx, cy, ox, oy, c_bs, o_bs, (uint32_t)n_cols, (uint32_t)log2L, batch, 2, s);
+            if (rc != HC_OK) return rc;
+            cx = ox;
+            cy = oy;
+            c_bs = o_bs;
+            a += M;
+        }
+        // 3. fused inner adjoint: w_hat rows -> gx~, gy~ rows
+        rc = launch_fused_adj<T>(K, xt, yt, W, gx ? gxt : nullptr, gy ? gyt : nullptr, P.xt_elems, P.n3,
+                                 P.xt_elems, (uint32_t)pow3u(P.p), batch, cus, s);
+        if (rc != HC_OK) return rc;
+        // 4. F^T on the outer axes, descending groups (reverse of the forward)
+        const T* ix = gxt;
+        const T* iy = gyt;
+        uint64_t i_bs = P.xt_elems;
+        int top = P.p;
+        for (int i = n - 1; i >= 0; --i) {
+            const int M = P.k1[i];
+            const int a0 = top - M;  // group [a0, top)
+            T* ox;
+            T* oy;
+            uint64_t o_bs;
+            if (i == 0) {
+                ox = gx;
+                oy = gy;
+                o_bs = P.n2;
+            } else if (((n - 1 - i) & 1) == 0) {
+                ox = gxtmp;
+                oy = gytmp;
+                o_bs = g_e;
+            } else {
+                ox = gxt;
+                oy = gyt;
+                o_bs = P.xt_elems;
+            }
+            const int log2L = D - top;
+            const uint64_t n_cols = pow3u(a0) << log2L;
+            rc = launch_fwd_adj_pass<T>(M, gx ? ix : nullptr, gy ? iy : nullptr, gx ? ox : nullptr,
+                                        gy ? oy : nullptr, i_bs, o_bs, (uint32_t)n_cols, (uint32_t)log2L, batch, s);
+            if (rc != HC_OK) return rc;
+            ix = ox;
+            iy = oy;
+            i_bs = o_bs;
+            top = a0;
+        }
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    return HC_OK;
+}
+
+template int run_forward<double>(const Plan&, const double*, const double*, double*, int, double*, int, hipStream_t);
+template int run_forward<float>(const Plan&, const float*, const float*, float*, int, float*, int, hipStream_t);
+template int run_forward<uint64_t>(const Plan&, const uint64_t*, const uint64_t*, uint64_t*, int, uint64_t*, int,
+                                   hipStream_t);
+template int run_backward<double>(const Plan&, const double*, const double*, const double*, uint64_t, double*,
+                                  double*, int, double*, int, hipStream_t);
+template int run_backward<float>(const Plan&, const float*, const float*, const float*, uint64_t, float*, float*,
+                                 int, float*, int, hipStream_t);
+
+}  // namespace hc
+
+using namespace hc;
+
+// =================================================================== C ABI
+extern "C" {
+
+int hc_abi_version(void) { return HC_ABI_VERSION; }
+
+const char* hc_status_string(int status)
+{
+    switch (status) {
+        case HC_OK: return "ok";
+        case HC_ERR_INVALID_ARG: return "invalid argument";
+        case HC_ERR_D_RANGE: return "D out of range";
+        case HC_ERR_UNSUPPORTED: return "unsupported dtype or configuration";
+        case HC_ERR_ALIAS: return "output overlaps an input or the workspace";
+        case HC_ERR_MISALIGNED: return "pointer not 16-byte aligned";
+        case HC_ERR_WORKSPACE: return "workspace missing or too small";
+        case HC_ERR_NO_DEVICE: return "no HIP device";
+        case HC_ERR_HIP: return "HIP runtime error";
+        default: return "unknown status";
+    }
+}
+
+const char* hc_last_error(void) { return g_last_error.c_str(); }
+
+size_t hc_dtype_size(int dtype) { return dtype_size(dtype); }
+
+uint64_t hc_output_count(int D) { return (D < 0 || D > HC_MAX_D) ? 0 : pow3u(D); }
+
+size_t hc_workspace_bytes(int D, int dtype, int batch)
+{
+    if (D < 0 || D > HC_MAX_D || dtype_size(dtype) == 0 || batch < 1) return (size_t)-1;
+    return plan_ws_bytes(make_plan(D, dtype, default_opts()), batch);
+}
+
+size_t hc_backward_workspace_bytes(int D, int dtype, int batch)
+{
+    if (D < 0 || D > HC_MAX_D || dtype_size(dtype) == 0 || batch < 1) return (size_t)-1;
+    return plan_bwd_ws_bytes(make_plan(D, dtype, default_opts(true)), batch);
+}
+
+int hc_convolve_batch(const void* x, const void* y, void* z, int D, int dtype, int batch, void* workspace,
+                      size_t workspace_bytes, hipStream_t stream)
+{
+    g_last_error.clear();
+    if (!x || !y || !z) return fail(HC_ERR_INVALID_ARG, "x, y and z must be non-null");
+    if (D < 0 || D > HC_MAX_D) return fail(HC_ERR_D_RANGE, "D=%d outside [0, %d]", D, HC_MAX_D);
+    const size_t es = dtype_size(dtype);
+    if (es == 0) return fail(HC_ERR_UNSUPPORTED, "unknown dtype %d", dtype);
+    if (batch < 1 || batch > 65535) return fail(HC_ERR_INVALID_ARG, "batch=%d outside [1, 65535]", batch);
+    if (misaligned(x) || misaligned(y) || misaligned(z) || misaligned(workspace))
+        return fail(HC_ERR_MISALIGNED, "pointers must be 16-byte aligned");
+    const Plan P = make_plan(D, dtype, default_opts());
+    const size_t in_b = (size_t)batch * P.n2 * es, out_b = (size_t)batch * P.n3 * es;
+    const size_t need = plan_ws_bytes(P, batch);
+    if (ranges_overlap(z, out_b, x, in_b) || ranges_overlap(z, out_b, y, in_b))
+        return fail(HC_ERR_ALIAS, "z overlaps x or y");
+    if (need > 0) {
+        if (!workspace || workspace_bytes < need)
+            return fail(HC_ERR_WORKSPACE, "workspace of %zu bytes required, %zu given", need,
+                        workspace ? workspace_bytes : (size_t)0);
+        if (ranges_overlap(z, out_b, workspace, need)) return fail(HC_ERR_ALIAS, "z overlaps the workspace");
+        if (ranges_overlap(workspace, need, x, in_b) || ranges_overlap(workspace, need, y, in_b))
+            return fail(HC_ERR_ALIAS, "workspace overlaps x or y");
+    }
+    int cus = 0;
+    int rc = device_cus(&cus);
+    if (rc != HC_OK) return rc;
+    switch (dtype) {
+        case HC_F64:
+            return run_forward<double>(P, (const double*)x, (const double*)y, (double*)z, batch, (double*)workspace,
+                                       cus, stream);
+        case HC_F32:
+            return run_forward<float>(P, (const float*)x, (const float*)y, (float*)z, batch, (float*)workspace, cus,
+                                      stream);
+        default:
+            return run_forward<uint64_t>(P, (const uint64_t*)x, (const uint64_t*)y, (uint64_t*)z, batch,
+                                         (uint64_t*)workspace, cus, stream);
+    }
+}
+
+int hc_convolve(const void* x, const void* y, void* z, int D, int dtype, void* workspace, size_t workspace_bytes,
+                hipStream_t stream)
+{
+    return hc_convolve_batch(x, y, z, D, dtype, 1, workspace, workspace_bytes, stream);
+}
+
+int hc_convolve_backward_batch(const void* x, const void* y, const void* grad_z, int64_t grad_z_stride,
+                               void* grad_x, void* grad_y, int D, int dtype, int batch, void* workspace,
+                               size_t workspace_bytes, hipStream_t stream)
+{
+    g_last_error.clear();
+    if (!x || !y || !grad_z) return fail(HC_ERR_INVALID_ARG, "x, y and grad_z must be non-null");
+    if (!grad_x && !grad_y) return fail(HC_ERR_INVALID_ARG, "at least one of grad_x, grad_y is required");
+    if (D < 0 || D > HC_MAX_D) return fail(HC_ERR_D_RANGE, "D=%d outside [0, %d]", D, HC_MAX_D);
+    const size_t es = dtype_size(dtype);
+    if (es == 0) return fail(HC_ERR_UNSUPPORTED, "unknown dtype %d", dtype);
+    if (dtype == HC_I64) return fail(HC_ERR_UNSUPPORTED, "the backward pass supports float64 and float32 only");
+    if (batch < 1 || batch > 65535) return fail(HC_ERR_INVALID_ARG, "batch=%d outside [1, 65535]", batch);
+    const Plan P = make_plan(D, dtype, default_opts(true));
+    if (grad_z_stride != 0 && (grad_z_stride < 0 || (uint64_t)grad_z_stride < P.n3))
+        return fail(HC_ERR_INVALID_ARG, "grad_z_stride must be 0 or at least 3^D");
+    if (misaligned(x) || misaligned(y) || misaligned(grad_z) || misaligned(grad_x) || misaligned(grad_y) ||
+        misaligned(workspace))
+        return fail(HC_ERR_MISALIGNED, "pointers must be 16-byte aligned");
+    const size_t in_b = (size_t)batch * P.n2 * es;
+    const size_t gz_b = (grad_z_stride == 0 ? P.n3 : (size_t)grad_z_stride * (batch - 1) + P.n3) * es;
+    const size_t need = plan_bwd_ws_bytes(P, batch);
+    const void* ins[3] = {x, y, grad_z};
+    const size_t ins_b[3] = {in_b, in_b, gz_b};
+    void* outs[2] = {grad_x, grad_y};
+    for (void* o : outs) {
+        if (!o) continue;
+        for (int i = 0; i < 3; ++i)
+            if (ranges_overlap(o, in_b, ins[i], ins_b[i])) return fail(HC_ERR_ALIAS, "a gradient overlaps an input");
+        if (need && ranges_overlap(o, in_b, workspace, need))
+            return fail(HC_ERR_ALIAS, "a gradient overlaps the workspace");
+    }
+    if (grad_x && grad_y && ranges_overlap(grad_x, in_b, grad_y, in_b))
+        return fail(HC_ERR_ALIAS, "grad_x overlaps grad_y");
+    if (need > 0) {
+        if (!workspace || workspace_bytes < need)
+            return fail(HC_ERR_WORKSPACE, "workspace of %zu bytes required, %zu given", need,
+                        workspace ? workspace_bytes : (size_t)0);
+        for (int i = 0; i < 3; ++i)
+            if (ranges_overlap(workspace, need, ins[i], ins_b[i]))
+                return fail(HC_ERR_ALIAS, "workspace overlaps an input");
+    }
+    int cus = 0;
+    int rc = device_cus(&cus);
+    if (rc != HC_OK) return rc;
+    if (dtype == HC_F64)
+        return run_backward<double>(P, (const double*)x, (const double*)y, (const double*)grad_z,
+                                    (uint64_t)grad_z_stride, (double*)grad_x, (double*)grad_y, batch,
+                                    (double*)workspace, cus, stream);
+    return run_backward<float>(P, (const float*)x, (const float*)y, (const float*)grad_z, (uint64_t)grad_z_stride,
+                               (float*)grad_x, (float*)grad_y, batch, (float*)workspace, cus, stream);
+}
+
+int hc_convolve_backward(const void* x, const void* y, const void* grad_z, void* grad_x, void* grad_y, int D,
+                         int dtype, void* workspace, size_t workspace_bytes, hipStream_t stream)
+{
+    return hc_convolve_backward_batch(x, y, grad_z, 0, grad_x, grad_y, D, dtype, 1, workspace, workspace_bytes,
+                                      stream);
+}
+
+int hc_profile_enable(int on)
+{
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof_on = on != 0;
+    return HC_OK;
+}
+
+int hc_profile_collect(hc_kernel_stat* out, int capacity, int* count)
+{
+    g_last_error.clear();
+    if (!count || (capacity > 0 && !out)) return fail(HC_ERR_INVALID_ARG, "count and out are required");
+    std::vector<ProfRec> recs;
+    {
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        recs.swap(g_prof);
+    }
+    std::vector<hc_kernel_stat> agg;
+    int rc = HC_OK;
+    for (ProfRec& r : recs) {
+        float ms = 0.f;
+        hipError_t e = hipEventSynchronize(r.b);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, r.a, r.b);
+        if (e != hipSuccess && rc == HC_OK) rc = hip_fail(e, "profiler events");
+        hc_kernel_stat* st = nullptr;
+        for (hc_kernel_stat& a : agg)
+            if (strncmp(a.name, r.name, sizeof(a.name)) == 0) st = &a;
+        if (!st) {
+            agg.push_back(hc_kernel_stat{});
+            st = &agg.back();
+            snprintf(st->name, sizeof(st->name), "%s", r.name);
+        }
+        st->launches += 1;
+        st->total_ms += ms;
+        st->alg_bytes += r.bytes;
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        for (ProfRec& r : recs) {
+            g_event_pool.push_back(r.a);
+            g_event_pool.push_back(r.b);
+        }
+    }
+    const int n = (int)agg.size() < capacity ? (int)agg.size() : capacity;
+    for (int i = 0; i < n; ++i) out[i] = agg[i];
+    *count = n;
+    return rc;
+}
+
+}  // extern "C"

@@ -1,0 +1,73 @@
+// Internal host-side declarations shared by the libhc translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include <vector>
+
+namespace hc {
+
+// One outer inverse pass: G on axes [a, a + mB + mA); group B = [a, a + mB)
+// (processed second), group A = [a + mB, a + mB + mA) (processed first).
+// C = columns per tile for the LDS variant (mB > 0).
+struct InvPass {
+    int a = 0, mA = 0, mB = 0, C = 16;
+};
+
+// Tuning knobs; zero means "use the default".
+struct PlanOpts {
+    int fused_depth = 0;     // K: inner axes fused in one tile
+    int inv_group_max = 0;   // largest outer inverse group
+    int inv_cols = 0;        // columns per LDS tile of an inverse pass
+    int inv_reg_max = 4;     // groups up to this size stay register-only
+    bool inv_reg_only = false;
+    bool backward = false;   // plan for the adjoint kernels (fused depth <= 8)
+};
+
+struct Plan {
+    int D = 0, dtype = 0;
+    size_t esize = 0;
+    int K = 0, p = 0;                 // fused inner depth, outer axes
+    std::vector<int> k1;              // outer forward groups, ascending from axis 0
+    std::vector<InvPass> inv;         // outer inverse passes in execution order
+    uint64_t n2 = 0, n3 = 0;
+    uint64_t xt_elems = 0;            // 3^p * 2^K per operand and batch item
+    uint64_t tmp_elems = 0;           // largest outer-forward staging stage
+};
+
+// Brackets one kernel launch with profiler events when profiling is on.
+class LaunchScope {
+  public:
+    LaunchScope(hipStream_t s, double alg_bytes, const char* fmt, ...);
+    ~LaunchScope();
+    LaunchScope(const LaunchScope&) = delete;
+    LaunchScope& operator=(const LaunchScope&) = delete;
+
+  private:
+    hipStream_t stream_;
+    bool on_;
+    size_t idx_;
+};
+
+int fail(int code, const char* fmt, ...);
+int hip_fail(hipError_t e, const char* what);
+uint64_t pow3u(int n);
+size_t dtype_size(int dtype);
+bool ranges_overlap(const void* a, size_t na, const void* b, size_t nb);
+bool misaligned(const void* p);
+int device_cus(int* cus);
+int max_fused_depth(int dtype);
+Plan make_plan(int D, int dtype, const PlanOpts& o);
+PlanOpts default_opts(bool backward = false);
+size_t plan_ws_bytes(const Plan& P, int batch);
+size_t plan_bwd_ws_bytes(const Plan& P, int batch);
+
+template <typename T>
+int run_forward(const Plan& P, const T* x, const T* y, T* z, int batch, T* ws, int cus, hipStream_t s);
+template <typename T>
+int run_backward(const Plan& P, const T* x, const T* y, const T* gz, uint64_t gz_bs, T* gx, T* gy, int batch,
+                 T* ws, int cus, hipStream_t s);
+
+}  // namespace hc
