@@ -174,6 +174,7 @@ Plan make_plan(int D, int dtype, const PlanOpts& o)
     if (K > D) K = D;
     P.K = K;
     P.p = D - K;
+    P.grid_per_cu = o.grid_per_cu;
     P.n2 = 1ull << D;
     P.n3 = pow3u(D);
     // outer forward groups (ascending), at most 4 axes each, balanced
@@ -186,23 +187,18 @@ Plan make_plan(int D, int dtype, const PlanOpts& o)
             left -= m;
         }
     }
-    // outer inverse passes (descending), groups of at most max_m axes
-    const int max_m = o.inv_group_max > 0 ? o.inv_group_max : 6;
+    // outer inverse passes (descending), groups of at most max_m axes, of
+    // which at most reg axes in registers and at most 2 across waves
+    const int reg = o.inv_reg > 0 ? cmin(o.inv_reg, 4) : 4;
+    const int max_m = cmin(o.inv_group_max > 0 ? o.inv_group_max : 6, reg + 2);
     int top = P.p;  // axes [0, top) still to invert
     while (top > 0) {
         const int m = top < max_m ? top : max_m;
         const int a = top - m;
         InvPass ip;
         ip.a = a;
-        if (m <= 4 && (o.inv_reg_only || m <= o.inv_reg_max)) {
-            ip.mA = m;
-            ip.mB = 0;
-        } else {
-            ip.mA = 3;
-            ip.mB = m - 3;
-            if (ip.mB > 3) { ip.mA = m - 3; ip.mB = 3; }
-        }
-        ip.C = o.inv_cols > 0 ? o.inv_cols : 16;
+        ip.mR = m < reg ? m : reg;
+        ip.mW = m - ip.mR;
         P.inv.push_back(ip);
         top = a;
     }
@@ -227,8 +223,8 @@ PlanOpts default_opts(bool backward)
     o.backward = backward;
     if (const char* s = getenv("HC_FUSED_K")) o.fused_depth = atoi(s);
     if (const char* s = getenv("HC_INV_MAXM")) o.inv_group_max = atoi(s);
-    if (const char* s = getenv("HC_INV_COLS")) o.inv_cols = atoi(s);
-    if (const char* s = getenv("HC_INV_REG")) o.inv_reg_only = atoi(s) != 0;
+    if (const char* s = getenv("HC_INV_REG")) o.inv_reg = atoi(s);
+    if (const char* s = getenv("HC_GRID_PER_CU")) o.grid_per_cu = atoi(s);
     return o;
 }
 
@@ -314,20 +310,30 @@ int launch_fwd_adj_pass(int M, const T* in0, const T* in1, T* out0, T* out1, uin
     return HC_OK;
 }
 
+// Workgroups for n_tiles tiles.  per_cu == 0: one tile per workgroup (short
+// workgroups that stream one tile and exit keep HBM busiest); the count is
+// rounded up to a multiple of 8 so that the XCD-aware walk hands every XCD
+// one contiguous chunk.  per_cu > 0: a persistent grid of at most that many
+// workgroups per CU, each looping over tiles.
 static uint32_t tile_grid(uint64_t n_tiles, int cus, int per_cu)
 {
-    uint64_t cap = (uint64_t)cus * per_cu;
-    uint64_t g = n_tiles < cap ? n_tiles : cap;
-    if (g >= 8) g &= ~7ull;
+    uint64_t g = n_tiles;
+    if (per_cu > 0) {
+        const uint64_t cap = (uint64_t)cus * per_cu;
+        if (g > cap) g = cap;
+        if (g >= 8) g &= ~7ull;
+    } else if (g >= 8) {
+        g = (g + 7) & ~7ull;
+    }
     return (uint32_t)(g ? g : 1);
 }
 
 template <typename T, int K>
 static void launch_fused_k(const T* xt, const T* yt, T* z, uint64_t in_bs, uint64_t z_bs, uint32_t n_tiles,
-                           int batch, int cus, hipStream_t s)
+                           int batch, int cus, int per_cu, hipStream_t s)
 {
     constexpr int NT = 256;
-    dim3 grid(tile_grid(n_tiles, cus, 16), batch, 1);
+    dim3 grid(tile_grid(n_tiles, cus, per_cu), batch, 1);
     const double bytes = (double)batch * n_tiles * (2.0 * (1 << K) + pow3c(K)) * sizeof(T);
     LaunchScope scope(s, bytes, "fused_inner<%s,K=%d>", tname<T>(), K);
     k_fused_inner<T, K, NT><<<grid, NT, 0, s>>>(xt, yt, z, in_bs, z_bs, n_tiles);
@@ -335,21 +341,21 @@ static void launch_fused_k(const T* xt, const T* yt, T* z, uint64_t in_bs, uint6
 
 template <typename T>
 int launch_fused(int K, const T* xt, const T* yt, T* z, uint64_t in_bs, uint64_t z_bs, uint32_t n_tiles,
-                  int batch, int cus, hipStream_t s)
+                  int batch, int cus, int per_cu, hipStream_t s)
 {
     switch (K) {
-        case 0: launch_fused_k<T, 0>(xt, yt, z, in_bs, z_bs, n_tiles, batch, cus, s); break;
-        case 1: launch_fused_k<T, 1>(xt, yt, z, in_bs, z_bs, n_tiles, batch, cus, s); break;
-        case 2: launch_fused_k<T, 2>(xt, yt, z, in_bs, z_bs, n_tiles, batch, cus, s); break;
-        case 3: launch_fused_k<T, 3>(xt, yt, z, in_bs, z_bs, n_tiles, batch, cus, s); break;
-        case 4: launch_fused_k<T, 4>(xt, yt, z, in_bs, z_bs, n_tiles, batch, cus, s); break;
-        case 5: launch_fused_k<T, 5>(xt, yt, z, in_bs, z_bs, n_tiles, batch, cus, s); break;
-        case 6: launch_fused_k<T, 6>(xt, yt, z, in_bs, z_bs, n_tiles, batch, cus, s); break;
-        case 7: launch_fused_k<T, 7>(xt, yt, z, in_bs, z_bs, n_tiles, batch, cus, s); break;
-        case 8: launch_fused_k<T, 8>(xt, yt, z, in_bs, z_bs, n_tiles, batch, cus, s); break;
+        case 0: launch_fused_k<T, 0>(xt, yt, z, in_bs, z_bs, n_tiles, batch, cus, per_cu, s); break;
+        case 1: launch_fused_k<T, 1>(xt, yt, z, in_bs, z_bs, n_tiles, batch, cus, per_cu, s); break;
+        case 2: launch_fused_k<T, 2>(xt, yt, z, in_bs, z_bs, n_tiles, batch, cus, per_cu, s); break;
+        case 3: launch_fused_k<T, 3>(xt, yt, z, in_bs, z_bs, n_tiles, batch, cus, per_cu, s); break;
+        case 4: launch_fused_k<T, 4>(xt, yt, z, in_bs, z_bs, n_tiles, batch, cus, per_cu, s); break;
+        case 5: launch_fused_k<T, 5>(xt, yt, z, in_bs, z_bs, n_tiles, batch, cus, per_cu, s); break;
+        case 6: launch_fused_k<T, 6>(xt, yt, z, in_bs, z_bs, n_tiles, batch, cus, per_cu, s); break;
+        case 7: launch_fused_k<T, 7>(xt, yt, z, in_bs, z_bs, n_tiles, batch, cus, per_cu, s); break;
+        case 8: launch_fused_k<T, 8>(xt, yt, z, in_bs, z_bs, n_tiles, batch, cus, per_cu, s); break;
         case 9:
             if constexpr (sizeof(T) == 4) {
-                launch_fused_k<T, 9>(xt, yt, z, in_bs, z_bs, n_tiles, batch, cus, s);
+                launch_fused_k<T, 9>(xt, yt, z, in_bs, z_bs, n_tiles, batch, cus, per_cu, s);
                 break;
             }
             return fail(HC_ERR_UNSUPPORTED, "no fused tile of 9 axes for 8-byte elements");
@@ -360,10 +366,11 @@ int launch_fused(int K, const T* xt, const T* yt, T* z, uint64_t in_bs, uint64_t
 
 template <typename T, int K>
 static void launch_fused_adj_k(const T* xt, const T* yt, const T* w, T* gxt, T* gyt, uint64_t in_bs,
-                               uint64_t w_bs, uint64_t g_bs, uint32_t n_tiles, int batch, int cus, hipStream_t s)
+                               uint64_t w_bs, uint64_t g_bs, uint32_t n_tiles, int batch, int cus, int per_cu,
+                               hipStream_t s)
 {
     constexpr int NT = 256;
-    dim3 grid(tile_grid(n_tiles, cus, 16), batch, 1);
+    dim3 grid(tile_grid(n_tiles, cus, per_cu), batch, 1);
     const int ops = (gxt ? 1 : 0) + (gyt ? 1 : 0);
     const double bytes = (double)batch * n_tiles * ((2.0 + ops) * (1 << K) + pow3c(K)) * sizeof(T);
     LaunchScope scope(s, bytes, "fused_inner_adj<%s,K=%d>", tname<T>(), K);
@@ -372,107 +379,58 @@ static void launch_fused_adj_k(const T* xt, const T* yt, const T* w, T* gxt, T* 
 
 template <typename T>
 int launch_fused_adj(int K, const T* xt, const T* yt, const T* w, T* gxt, T* gyt, uint64_t in_bs,
-                      uint64_t w_bs, uint64_t g_bs, uint32_t n_tiles, int batch, int cus, hipStream_t s)
+                      uint64_t w_bs, uint64_t g_bs, uint32_t n_tiles, int batch, int cus, int per_cu, hipStream_t s)
 {
     switch (K) {
-        case 0: launch_fused_adj_k<T, 0>(xt, yt, w, gxt, gyt, in_bs, w_bs, g_bs, n_tiles, batch, cus, s); break;
-        case 1: launch_fused_adj_k<T, 1>(xt, yt, w, gxt, gyt, in_bs, w_bs, g_bs, n_tiles, batch, cus, s); break;
-        case 2: launch_fused_adj_k<T, 2>(xt, yt, w, gxt, gyt, in_bs, w_bs, g_bs, n_tiles, batch, cus, s); break;
-        case 3: launch_fused_adj_k<T, 3>(xt, yt, w, gxt, gyt, in_bs, w_bs, g_bs, n_tiles, batch, cus, s); break;
-        case 4: launch_fused_adj_k<T, 4>(xt, yt, w, gxt, gyt, in_bs, w_bs, g_bs, n_tiles, batch, cus, s); break;
-        case 5: launch_fused_adj_k<T, 5>(xt, yt, w, gxt, gyt, in_bs, w_bs, g_bs, n_tiles, batch, cus, s); break;
-        case 6: launch_fused_adj_k<T, 6>(xt, yt, w, gxt, gyt, in_bs, w_bs, g_bs, n_tiles, batch, cus, s); break;
-        case 7: launch_fused_adj_k<T, 7>(xt, yt, w, gxt, gyt, in_bs, w_bs, g_bs, n_tiles, batch, cus, s); break;
-        case 8: launch_fused_adj_k<T, 8>(xt, yt, w, gxt, gyt, in_bs, w_bs, g_bs, n_tiles, batch, cus, s); break;
+        case 0: launch_fused_adj_k<T, 0>(xt, yt, w, gxt, gyt, in_bs, w_bs, g_bs, n_tiles, batch, cus, per_cu, s); break;
+        case 1: launch_fused_adj_k<T, 1>(xt, yt, w, gxt, gyt, in_bs, w_bs, g_bs, n_tiles, batch, cus, per_cu, s); break;
+        case 2: launch_fused_adj_k<T, 2>(xt, yt, w, gxt, gyt, in_bs, w_bs, g_bs, n_tiles, batch, cus, per_cu, s); break;
+        case 3: launch_fused_adj_k<T, 3>(xt, yt, w, gxt, gyt, in_bs, w_bs, g_bs, n_tiles, batch, cus, per_cu, s); break;
+        case 4: launch_fused_adj_k<T, 4>(xt, yt, w, gxt, gyt, in_bs, w_bs, g_bs, n_tiles, batch, cus, per_cu, s); break;
+        case 5: launch_fused_adj_k<T, 5>(xt, yt, w, gxt, gyt, in_bs, w_bs, g_bs, n_tiles, batch, cus, per_cu, s); break;
+        case 6: launch_fused_adj_k<T, 6>(xt, yt, w, gxt, gyt, in_bs, w_bs, g_bs, n_tiles, batch, cus, per_cu, s); break;
+        case 7: launch_fused_adj_k<T, 7>(xt, yt, w, gxt, gyt, in_bs, w_bs, g_bs, n_tiles, batch, cus, per_cu, s); break;
+        case 8: launch_fused_adj_k<T, 8>(xt, yt, w, gxt, gyt, in_bs, w_bs, g_bs, n_tiles, batch, cus, per_cu, s); break;
         default: return fail(HC_ERR_UNSUPPORTED, "no adjoint fused tile of %d axes", K);
     }
     return HC_OK;
 }
 
-template <typename T, int mA, int mB, int C, int NT>
-static void launch_inv_pass_v(T* z, uint64_t z_bs, uint64_t L, uint32_t n_hi, int batch, int cus, hipStream_t s)
+template <typename T, int mR, int mW, bool ADJ>
+static void launch_pass_v(const T* src, T* dst, uint64_t src_bs, uint64_t dst_bs, uint64_t L, uint32_t n_hi,
+                          int batch, int cus, int per_cu, hipStream_t s)
 {
-    const uint32_t cols = mB == 0 ? NT : C;
-    const uint32_t tiles_per_hi = (uint32_t)((L + cols - 1) / cols);
+    // register-only passes take 4 waves x 64 columns per workgroup; passes
+    // with a wave part take one wave per digit vector of that part
+    constexpr int CW = mW == 0 ? 4 : 1;
+    using PC = PassCfg<mR, mW, CW>;
+    const uint32_t tiles_per_hi = (uint32_t)((L + PC::COLS - 1) / PC::COLS);
     const uint64_t n_tiles = (uint64_t)tiles_per_hi * n_hi;
-    dim3 grid(tile_grid(n_tiles, cus, 16), batch, 1);
-    // reads every entry; writes those with a 1 among the group digits
-    const double n_all = (double)batch * n_hi * L;
-    const double bytes = n_all * (pow3c(mA + mB) + (pow3c(mA + mB) - (1 << (mA + mB)))) * sizeof(T);
-    LaunchScope scope(s, bytes, "inv_pass<%s,%d+%d,C=%d>", tname<T>(), mB, mA, mB ? C : NT);
-    k_inv_pass<T, mA, mB, C, NT><<<grid, NT, 0, s>>>(z, z_bs, L, tiles_per_hi, (uint32_t)n_tiles);
+    dim3 grid(tile_grid(n_tiles, cus, per_cu), batch, 1);
+    // reads every entry; writes the entries the map changes (all if out of place)
+    constexpr int TM = pow3c(mR + mW);
+    const double n_cols = (double)batch * n_hi * L;
+    const double writes = src != dst ? TM : (ADJ ? TM - 1 : TM - (1 << (mR + mW)));
+    const double bytes = n_cols * (TM + writes) * sizeof(T);
+    LaunchScope scope(s, bytes, "%s<%s,%d+%d>", ADJ ? "inv_adj_pass" : "inv_pass", tname<T>(), mR, mW);
+    k_inv_pass<T, mR, mW, CW, ADJ><<<grid, PC::NT, 0, s>>>(src, dst, src_bs, dst_bs, L, tiles_per_hi,
+                                                           (uint32_t)n_tiles);
 }
 
-template <typename T>
-int launch_inv_pass(const InvPass& ip, T* z, uint64_t z_bs, uint64_t L, uint32_t n_hi, int batch, int cus,
-                    hipStream_t s)
+template <typename T, bool ADJ>
+int launch_pass(const InvPass& ip, const T* src, T* dst, uint64_t src_bs, uint64_t dst_bs, uint64_t L, uint32_t n_hi,
+                int batch, int cus, int per_cu, hipStream_t s)
 {
-    const int key = ip.mA * 100 + ip.mB * 10;
-    if (ip.mB == 0) {
-        switch (ip.mA) {
-            case 1: launch_inv_pass_v<T, 1, 0, 1, 256>(z, z_bs, L, n_hi, batch, cus, s); return HC_OK;
-            case 2: launch_inv_pass_v<T, 2, 0, 1, 256>(z, z_bs, L, n_hi, batch, cus, s); return HC_OK;
-            case 3: launch_inv_pass_v<T, 3, 0, 1, 256>(z, z_bs, L, n_hi, batch, cus, s); return HC_OK;
-            case 4: launch_inv_pass_v<T, 4, 0, 1, 256>(z, z_bs, L, n_hi, batch, cus, s); return HC_OK;
-            default: break;
-        }
-    } else if (ip.C == 16) {
-        switch (key) {
-            case 310: launch_inv_pass_v<T, 3, 1, 16, 448>(z, z_bs, L, n_hi, batch, cus, s); return HC_OK;
-            case 320: launch_inv_pass_v<T, 3, 2, 16, 448>(z, z_bs, L, n_hi, batch, cus, s); return HC_OK;
-            case 330: launch_inv_pass_v<T, 3, 3, 16, 448>(z, z_bs, L, n_hi, batch, cus, s); return HC_OK;
-            default: break;
-        }
-    } else if (ip.C == 8) {
-        switch (key) {
-            case 310: launch_inv_pass_v<T, 3, 1, 8, 256>(z, z_bs, L, n_hi, batch, cus, s); return HC_OK;
-            case 320: launch_inv_pass_v<T, 3, 2, 8, 256>(z, z_bs, L, n_hi, batch, cus, s); return HC_OK;
-            case 330: launch_inv_pass_v<T, 3, 3, 8, 256>(z, z_bs, L, n_hi, batch, cus, s); return HC_OK;
-            default: break;
-        }
+#define HC_PASS(R, W) \
+    if (ip.mR == R && ip.mW == W) { \
+        launch_pass_v<T, R, W, ADJ>(src, dst, src_bs, dst_bs, L, n_hi, batch, cus, per_cu, s); \
+        return HC_OK; \
     }
-    return fail(HC_ERR_UNSUPPORTED, "no inverse-pass variant for groups (%d, %d) with %d columns", ip.mA, ip.mB,
-                ip.C);
-}
-
-template <typename T, int mA, int mB, int C, int NT>
-static void launch_inv_adj_pass_v(const T* src, T* dst, uint64_t src_bs, uint64_t dst_bs, uint64_t L,
-                                  uint32_t n_hi, int batch, int cus, hipStream_t s)
-{
-    const uint32_t cols = mB == 0 ? NT : C;
-    const uint32_t tiles_per_hi = (uint32_t)((L + cols - 1) / cols);
-    const uint64_t n_tiles = (uint64_t)tiles_per_hi * n_hi;
-    dim3 grid(tile_grid(n_tiles, cus, 16), batch, 1);
-    const double n_all = (double)batch * n_hi * L;
-    const double writes = src == dst ? (pow3c(mA + mB) - 1) : pow3c(mA + mB);
-    const double bytes = n_all * (pow3c(mA + mB) + writes) * sizeof(T);
-    LaunchScope scope(s, bytes, "inv_adj_pass<%s,%d+%d,C=%d>", tname<T>(), mB, mA, mB ? C : NT);
-    k_inv_adj_pass<T, mA, mB, C, NT><<<grid, NT, 0, s>>>(src, dst, src_bs, dst_bs, L, tiles_per_hi,
-                                                         (uint32_t)n_tiles);
-}
-
-template <typename T>
-int launch_inv_adj_pass(const InvPass& ip, const T* src, T* dst, uint64_t src_bs, uint64_t dst_bs, uint64_t L,
-                        uint32_t n_hi, int batch, int cus, hipStream_t s)
-{
-    const int key = ip.mA * 100 + ip.mB * 10;
-    if (ip.mB == 0) {
-        switch (ip.mA) {
-            case 1: launch_inv_adj_pass_v<T, 1, 0, 1, 256>(src, dst, src_bs, dst_bs, L, n_hi, batch, cus, s); return HC_OK;
-            case 2: launch_inv_adj_pass_v<T, 2, 0, 1, 256>(src, dst, src_bs, dst_bs, L, n_hi, batch, cus, s); return HC_OK;
-            case 3: launch_inv_adj_pass_v<T, 3, 0, 1, 256>(src, dst, src_bs, dst_bs, L, n_hi, batch, cus, s); return HC_OK;
-            case 4: launch_inv_adj_pass_v<T, 4, 0, 1, 256>(src, dst, src_bs, dst_bs, L, n_hi, batch, cus, s); return HC_OK;
-            default: break;
-        }
-    } else {
-        switch (key) {
-            case 310: launch_inv_adj_pass_v<T, 3, 1, 16, 448>(src, dst, src_bs, dst_bs, L, n_hi, batch, cus, s); return HC_OK;
-            case 320: launch_inv_adj_pass_v<T, 3, 2, 16, 448>(src, dst, src_bs, dst_bs, L, n_hi, batch, cus, s); return HC_OK;
-            case 330: launch_inv_adj_pass_v<T, 3, 3, 16, 448>(src, dst, src_bs, dst_bs, L, n_hi, batch, cus, s); return HC_OK;
-            default: break;
-        }
-    }
-    return fail(HC_ERR_UNSUPPORTED, "no adjoint inverse-pass variant for groups (%d, %d)", ip.mA, ip.mB);
+    HC_PASS(1, 0) HC_PASS(2, 0) HC_PASS(3, 0) HC_PASS(4, 0)
+    HC_PASS(1, 1) HC_PASS(2, 1) HC_PASS(3, 1) HC_PASS(4, 1)
+    HC_PASS(1, 2) HC_PASS(2, 2) HC_PASS(3, 2) HC_PASS(4, 2)
+#undef HC_PASS
+    return fail(HC_ERR_UNSUPPORTED, "no inverse pass with %d register and %d wave axes", ip.mR, ip.mW);
 }
 
 // ------------------------------------------------------------ forward run
@@ -482,7 +440,7 @@ int run_forward(const Plan& P, const T* x, const T* y, T* z, int batch, T* ws, i
     const int D = P.D, K = P.K;
     int rc = HC_OK;
     if (P.p == 0) {
-        rc = launch_fused<T>(K, x, y, z, P.n2, P.n3, 1, batch, cus, s);
+        rc = launch_fused<T>(K, x, y, z, P.n2, P.n3, 1, batch, cus, P.grid_per_cu, s);
         if (rc != HC_OK) return rc;
     } else {
         T* xt = ws;
@@ -510,13 +468,13 @@ int run_forward(const Plan& P, const T* x, const T* y, T* z, int batch, T* ws, i
             c_bs = o_bs;
             a += M;
         }
-        rc = launch_fused<T>(K, xt, yt, z, P.xt_elems, P.n3, (uint32_t)pow3u(P.p), batch, cus, s);
+        rc = launch_fused<T>(K, xt, yt, z, P.xt_elems, P.n3, (uint32_t)pow3u(P.p), batch, cus, P.grid_per_cu, s);
         if (rc != HC_OK) return rc;
         for (const InvPass& ip : P.inv) {
-            const int m = ip.mA + ip.mB;
+            const int m = ip.mR + ip.mW;
             const uint64_t L = pow3u(D - ip.a - m);
             const uint32_t n_hi = (uint32_t)pow3u(ip.a);
-            rc = launch_inv_pass<T>(ip, z, P.n3, L, n_hi, batch, cus, s);
+            rc = launch_pass<T, false>(ip, z, z, P.n3, P.n3, L, n_hi, batch, cus, P.grid_per_cu, s);
             if (rc != HC_OK) return rc;
         }
     }
@@ -533,7 +491,7 @@ int run_backward(const Plan& P, const T* x, const T* y, const T* gz, uint64_t gz
     const int D = P.D, K = P.K;
     int rc = HC_OK;
     if (P.p == 0) {
-        rc = launch_fused_adj<T>(K, x, y, gz, gx, gy, P.n2, gz_bs, P.n2, 1, batch, cus, s);
+        rc = launch_fused_adj<T>(K, x, y, gz, gx, gy, P.n2, gz_bs, P.n2, 1, batch, cus, P.grid_per_cu, s);
         if (rc != HC_OK) return rc;
     } else {
         uint64_t w_e, g_e;
@@ -552,10 +510,10 @@ int run_backward(const Plan& P, const T* x, const T* y, const T* gz, uint64_t gz
         uint64_t src_bs = gz_bs;
         for (int i = (int)P.inv.size() - 1; i >= 0; --i) {
             const InvPass& ip = P.inv[i];
-            const int m = ip.mA + ip.mB;
+            const int m = ip.mR + ip.mW;
             const uint64_t L = pow3u(D - ip.a - m);
             const uint32_t n_hi = (uint32_t)pow3u(ip.a);
-            rc = launch_inv_adj_pass<T>(ip, src, W, src_bs, P.n3, L, n_hi, batch, cus, s);
+            rc = launch_pass<T, true>(ip, src, W, src_bs, P.n3, L, n_hi, batch, cus, P.grid_per_cu, s);
             if (rc != HC_OK) return rc;
             src = W;
             src_bs = P.n3;
@@ -583,7 +541,7 @@ int run_backward(const Plan& P, const T* x, const T* y, const T* gz, uint64_t gz
         }
         // 3. fused inner adjoint: w_hat rows -> gx~, gy~ rows
         rc = launch_fused_adj<T>(K, xt, yt, W, gx ? gxt : nullptr, gy ? gyt : nullptr, P.xt_elems, P.n3,
-                                 P.xt_elems, (uint32_t)pow3u(P.p), batch, cus, s);
+                                 P.xt_elems, (uint32_t)pow3u(P.p), batch, cus, P.grid_per_cu, s);
         if (rc != HC_OK) return rc;
         // 4. F^T on the outer axes, descending groups (reverse of the forward)
         const T* ix = gxt;

@@ -9,21 +9,21 @@
 
 namespace hc {
 
-// One outer inverse pass: G on axes [a, a + mB + mA); group B = [a, a + mB)
-// (processed second), group A = [a + mB, a + mB + mA) (processed first).
-// C = columns per tile for the LDS variant (mB > 0).
+// One outer inverse pass over the axes [a, a + mR + mW): mR axes held in
+// registers, mW axes across waves.  In the forward inverse (G, descending)
+// the register part is the group's inner axes; in the adjoint (G^T,
+// ascending) it is the group's outer axes.
 struct InvPass {
-    int a = 0, mA = 0, mB = 0, C = 16;
+    int a = 0, mR = 0, mW = 0;
 };
 
 // Tuning knobs; zero means "use the default".
 struct PlanOpts {
     int fused_depth = 0;     // K: inner axes fused in one tile
-    int inv_group_max = 0;   // largest outer inverse group
-    int inv_cols = 0;        // columns per LDS tile of an inverse pass
-    int inv_reg_max = 4;     // groups up to this size stay register-only
-    bool inv_reg_only = false;
+    int inv_group_max = 0;   // largest outer inverse group (at most 6)
+    int inv_reg = 0;         // axes of a group held in registers (at most 4)
     bool backward = false;   // plan for the adjoint kernels (fused depth <= 8)
+    int grid_per_cu = 0;     // 0: one tile per workgroup; else at most this many workgroups per CU
 };
 
 struct Plan {
@@ -35,6 +35,7 @@ struct Plan {
     uint64_t n2 = 0, n3 = 0;
     uint64_t xt_elems = 0;            // 3^p * 2^K per operand and batch item
     uint64_t tmp_elems = 0;           // largest outer-forward staging stage
+    int grid_per_cu = 0;              // launch policy, see PlanOpts
 };
 
 // Brackets one kernel launch with profiler events when profiling is on.

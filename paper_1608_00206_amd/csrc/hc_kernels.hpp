@@ -5,16 +5,19 @@
 //   z      3^D values, ternary digit of weight 3^d = axis D-1-d
 // The D axes are split into p = D - K outer axes and K inner axes.  The
 // forward path is
-//   outer forward   F on axes 0..p-1           x: 2^D -> 3^p x 2^K   (k_fwd_pass)
+//   outer forward   F on axes 0..p-1           x: 2^D -> 3^p x 2^K   (fwd_column)
 //   fused inner     per outer index o: F on axes p..D-1, product, G on axes
-//                   D-1..p, one contiguous 3^K row of z            (k_fused_inner)
-//   outer inverse   G on axes p-1..0 in groups, in place on z      (k_inv_pass)
+//                   D-1..p, one contiguous 3^K row of z            (fused_tile)
+//   outer inverse   G on axes p-1..0 in groups, in place on z      (inv_tile)
 // which applies every map in exactly the canonical axis order, so the result
 // is bitwise independent of K, of the grouping and of the tiling.
 //
 // The backward path (gradient of sum(w * z)) mirrors it with the transposed
-// maps: k_inv_adj_pass (G^T on outer axes, ascending), k_fused_inner_adj,
-// k_fwd_adj_pass (F^T on outer axes, descending).
+// maps: inv_tile<ADJ> (G^T on outer axes, ascending), fused_tile_adj,
+// fwd_adj_column (F^T on outer axes, descending).
+//
+// Each step is a device function working on one tile or column, called by
+// the single-problem kernels below and by the batched persistent kernel.
 #pragma once
 
 #include "hc_device.hpp"
@@ -24,22 +27,13 @@ namespace hc {
 // =========================================================================
 // Outer forward pass: F on M consecutive binary axes, out of place.
 //   in  [n_hi][2^M][L]   ->   out [n_hi][3^M][L],   L = 2^log2L
-// One thread per (hi, lo) column; lanes take consecutive lo, so every load and
-// store of a wave is one contiguous run.  blockIdx.y = batch item,
-// blockIdx.z = operand (0: x, 1: y).
+// One thread per (hi, lo) column c; lanes take consecutive lo, so every load
+// and store of a wave is one contiguous run.
 // =========================================================================
-template <typename T, int M, int NT>
-__global__ __launch_bounds__(NT) void k_fwd_pass(const T* __restrict__ in0, const T* __restrict__ in1,
-                                                 T* __restrict__ out0, T* __restrict__ out1,
-                                                 uint64_t in_bstride, uint64_t out_bstride,
-                                                 uint32_t n_cols, uint32_t log2L)
+template <typename T, int M>
+__device__ __forceinline__ void fwd_column(const T* __restrict__ in, T* __restrict__ out, uint32_t c,
+                                           uint32_t log2L)
 {
-    const T* in = blockIdx.z ? in1 : in0;
-    T* out = blockIdx.z ? out1 : out0;
-    in += (uint64_t)blockIdx.y * in_bstride;
-    out += (uint64_t)blockIdx.y * out_bstride;
-    const uint32_t c = blockIdx.x * NT + threadIdx.x;
-    if (c >= n_cols) return;
     const uint64_t L = 1ull << log2L;
     const uint64_t hi = c >> log2L;
     const uint64_t lo = c & (L - 1);
@@ -51,6 +45,20 @@ __global__ __launch_bounds__(NT) void k_fwd_pass(const T* __restrict__ in0, cons
     fwd_group<T, M>(s);
 #pragma unroll
     for (int t = 0; t < pow3c(M); ++t) dst[(uint64_t)t * L] = s[t];
+}
+
+// blockIdx.y = batch item, blockIdx.z = operand (0: x, 1: y).
+template <typename T, int M, int NT>
+__global__ __launch_bounds__(NT) void k_fwd_pass(const T* __restrict__ in0, const T* __restrict__ in1,
+                                                 T* __restrict__ out0, T* __restrict__ out1,
+                                                 uint64_t in_bstride, uint64_t out_bstride,
+                                                 uint32_t n_cols, uint32_t log2L)
+{
+    const T* in = blockIdx.z ? in1 : in0;
+    T* out = blockIdx.z ? out1 : out0;
+    const uint32_t c = blockIdx.x * NT + threadIdx.x;
+    if (c >= n_cols) return;
+    fwd_column<T, M>(in + (uint64_t)blockIdx.y * in_bstride, out + (uint64_t)blockIdx.y * out_bstride, c, log2L);
 }
 
 // =========================================================================
@@ -125,6 +133,82 @@ __device__ __forceinline__ void fused_forward_cb(const T* __restrict__ xr, const
     lds_barrier();
 }
 
+// One fused tile: rows xr, yr (2^K each) -> zr (3^K).  lds holds
+// FusedCfg<K>::LDS elements; the caller separates two tiles that reuse it by
+// an lds_barrier().  NT threads take part.
+template <typename T, int K, int NT>
+__device__ __forceinline__ void fused_tile(const T* __restrict__ xr, const T* __restrict__ yr, T* __restrict__ zr,
+                                           T* lds)
+{
+    using C = FusedCfg<K>;
+    T* R0 = lds;
+    T* R1 = R0 + 2 * C::R0h;
+    T* R2 = R1 + 2 * C::R1h;
+    T* Z = lds;  // aliases R0..R2; written only after R2 has been read
+    constexpr int N3I = C::tC * C::tB;  // P3 items
+    constexpr int IPT = (N3I + NT - 1) / NT;
+    const int tid = threadIdx.x;
+    fused_forward_cb<T, K, NT>(xr, yr, R0, R1, R2);
+    // P3: registers take this thread's R2 columns, then Z may overwrite R2
+    T xa[IPT][C::nA], ya[IPT][C::nA];
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) {
+        const int it = tid + j * NT;
+        if (it < N3I) {
+#pragma unroll
+            for (int bA = 0; bA < C::nA; ++bA) {
+                xa[j][bA] = R2[bA * N3I + it];
+                ya[j][bA] = R2[C::R2h + bA * N3I + it];
+            }
+        }
+    }
+    lds_barrier();
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) {
+        const int it = tid + j * NT;
+        if (it < N3I) {
+            T xs[pow3c(C::kA)], ys[pow3c(C::kA)];
+#pragma unroll
+            for (int bA = 0; bA < C::nA; ++bA) {
+                xs[bA] = xa[j][bA];
+                ys[bA] = ya[j][bA];
+            }
+            fwd_group<T, C::kA>(xs);
+            fwd_group<T, C::kA>(ys);
+#pragma unroll
+            for (int g = 0; g < C::tA; ++g) xs[g] = xs[g] * ys[g];
+            inv_group<T, C::kA>(xs);
+#pragma unroll
+            for (int g = 0; g < C::tA; ++g) Z[it * C::tA + g] = xs[g];
+        }
+    }
+    lds_barrier();
+    // P4: G on group B
+    if constexpr (C::kB > 0) {
+        for (int it = tid; it < C::tC * C::tA; it += NT) {
+            const int gC = it / C::tA;
+            const int gA = it - gC * C::tA;
+            T v[pow3c(C::kB)];
+#pragma unroll
+            for (int gB = 0; gB < C::tB; ++gB) v[gB] = Z[(gC * C::tB + gB) * C::tA + gA];
+            inv_group<T, C::kB>(v);
+#pragma unroll
+            for (int gB = 0; gB < C::tB; ++gB)
+                if (has_digit_one(gB, C::kB)) Z[(gC * C::tB + gB) * C::tA + gA] = v[gB];
+        }
+        lds_barrier();
+    }
+    // P5: G on group C and the contiguous store of the row
+    for (int it = tid; it < C::tB * C::tA; it += NT) {
+        T v[pow3c(C::kC)];
+#pragma unroll
+        for (int gC = 0; gC < C::tC; ++gC) v[gC] = Z[gC * (C::tB * C::tA) + it];
+        inv_group<T, C::kC>(v);
+#pragma unroll
+        for (int gC = 0; gC < C::tC; ++gC) zr[gC * (C::tB * C::tA) + it] = v[gC];
+    }
+}
+
 template <typename T, int K, int NT>
 __global__ __launch_bounds__(NT) void k_fused_inner(const T* __restrict__ xt, const T* __restrict__ yt,
                                                     T* __restrict__ z, uint64_t in_bstride,
@@ -132,264 +216,174 @@ __global__ __launch_bounds__(NT) void k_fused_inner(const T* __restrict__ xt, co
 {
     using C = FusedCfg<K>;
     __shared__ T lds[C::LDS];
-    T* R0 = lds;
-    T* R1 = R0 + 2 * C::R0h;
-    T* R2 = R1 + 2 * C::R1h;
-    T* Z = lds;  // aliases R0..R2; written only after R2 has been read
-    constexpr int N3I = C::tC * C::tB;                 // P3 items
-    constexpr int IPT = (N3I + NT - 1) / NT;
-    const int tid = threadIdx.x;
     xt += (uint64_t)blockIdx.y * in_bstride;
     yt += (uint64_t)blockIdx.y * in_bstride;
     z += (uint64_t)blockIdx.y * z_bstride;
-
     const TileWalk w = xcd_tile_walk(n_tiles);
     for (uint32_t o = w.first; o < w.end; o += w.step) {
         lds_barrier();  // the previous tile's P5 reads of Z are done
-        fused_forward_cb<T, K, NT>(xt + (uint64_t)o * C::N2, yt + (uint64_t)o * C::N2, R0, R1, R2);
-
-        // P3: registers take this thread's R2 columns, then Z may overwrite R2
-        T xa[IPT][C::nA], ya[IPT][C::nA];
-#pragma unroll
-        for (int j = 0; j < IPT; ++j) {
-            const int it = tid + j * NT;
-            if (it < N3I) {
-#pragma unroll
-                for (int bA = 0; bA < C::nA; ++bA) {
-                    xa[j][bA] = R2[bA * N3I + it];
-                    ya[j][bA] = R2[C::R2h + bA * N3I + it];
-                }
-            }
-        }
-        lds_barrier();
-#pragma unroll
-        for (int j = 0; j < IPT; ++j) {
-            const int it = tid + j * NT;
-            if (it < N3I) {
-                T xs[pow3c(C::kA)], ys[pow3c(C::kA)];
-#pragma unroll
-                for (int bA = 0; bA < C::nA; ++bA) {
-                    xs[bA] = xa[j][bA];
-                    ys[bA] = ya[j][bA];
-                }
-                fwd_group<T, C::kA>(xs);
-                fwd_group<T, C::kA>(ys);
-#pragma unroll
-                for (int g = 0; g < C::tA; ++g) xs[g] = xs[g] * ys[g];
-                inv_group<T, C::kA>(xs);
-#pragma unroll
-                for (int g = 0; g < C::tA; ++g) Z[it * C::tA + g] = xs[g];
-            }
-        }
-        lds_barrier();
-        // P4: G on group B
-        if constexpr (C::kB > 0) {
-            for (int it = tid; it < C::tC * C::tA; it += NT) {
-                const int gC = it / C::tA;
-                const int gA = it - gC * C::tA;
-                T v[pow3c(C::kB)];
-#pragma unroll
-                for (int gB = 0; gB < C::tB; ++gB) v[gB] = Z[(gC * C::tB + gB) * C::tA + gA];
-                inv_group<T, C::kB>(v);
-#pragma unroll
-                for (int gB = 0; gB < C::tB; ++gB)
-                    if (has_digit_one(gB, C::kB)) Z[(gC * C::tB + gB) * C::tA + gA] = v[gB];
-            }
-            lds_barrier();
-        }
-        // P5: G on group C and the contiguous store of row o
-        T* zr = z + (uint64_t)o * C::N3;
-        for (int it = tid; it < C::tB * C::tA; it += NT) {
-            T v[pow3c(C::kC)];
-#pragma unroll
-            for (int gC = 0; gC < C::tC; ++gC) v[gC] = Z[gC * (C::tB * C::tA) + it];
-            inv_group<T, C::kC>(v);
-#pragma unroll
-            for (int gC = 0; gC < C::tC; ++gC) zr[gC * (C::tB * C::tA) + it] = v[gC];
-        }
+        fused_tile<T, K, NT>(xt + (uint64_t)o * C::N2, yt + (uint64_t)o * C::N2, z + (uint64_t)o * C::N3, lds);
     }
 }
 
 // =========================================================================
-// Outer inverse pass: G on m = mB + mA consecutive axes, in place.
-//   z viewed as [n_hi][3^mB][3^mA][L],  L = 3^(axes below the group)
-// Group A (the group's inner mA axes) comes first in the descending order,
-// then group B.  A tile is C consecutive columns of one hi.
-//   mB == 0:  one thread per column, all 3^mA values in registers.
-//   mB >  0:  phase 1 thread per (gB, column) does G on A in registers and
-//             parks the tile in LDS; phase 2 thread per (gA, column) does G
-//             on B and stores.  Entries whose group digits contain no 1 are
-//             unchanged by G and are not written back.
+// Outer inverse pass (forward path: G, axes descending) and its adjoint
+// (backward path: G^T, axes ascending) on one group of m = mR + mW
+// consecutive axes, with z viewed as [n_hi][3^m][L], L = 3^(axes below).
+//
+// A tile is 64*CW consecutive columns lo of one hi and all 3^m rows.  The
+// group splits into a register part R (mR axes, 3^mR values per lane) and a
+// wave part W (mW axes, one wave per digit vector gW):
+//   phase 1   wave (cg, gW), lane l loads the 3^mR rows of its (gW, column)
+//             line and applies the map on R in registers.  Row bases are the
+//             same for all lanes of a wave, so each load is one 512 B run.
+//   phase 2   (mW > 0) the values cross to a per-gR layout through LDS in
+//             sub-rounds of S_GA register indices (double-buffered, one
+//             barrier each); wave w applies the map on W for its gR and stores.
+// Axis order: the forward inverse takes R = the group's inner axes (G runs
+// from the innermost axis out); the adjoint takes R = the group's outer axes
+// (G^T runs from the outermost axis in).  Row of (gOuter, gInner) =
+// gOuter * 3^(inner axes) + gInner in both cases.
+// Entries the map leaves unchanged are not stored when src == dst:
+//   G   changes entries with a 1 among the group digits,
+//   G^T changes entries whose group digits are not all 1.
+// Columns past L: a wave whose 64 columns all lie past L does nothing; other
+// lanes past L re-read and re-write their wave's first column with the value
+// that column's own lane computes (identical stores in the same instruction,
+// every access in bounds).
 // =========================================================================
-template <typename T, int mA, int mB, int C, int NT>
-__global__ __launch_bounds__(NT) void k_inv_pass(T* __restrict__ z, uint64_t z_bstride, uint64_t L,
-                                                 uint32_t tiles_per_hi, uint32_t n_tiles)
+template <int mR, int mW, int CW>
+struct PassCfg {
+    static_assert(mW == 0 || CW == 1, "several column groups only without the wave part");
+    static constexpr int tR = pow3c(mR), tW = pow3c(mW);
+    static constexpr int WAVES = tW * CW;
+    static constexpr int NT = 64 * WAVES;
+    static constexpr int COLS = 64 * CW;
+    static constexpr int S_GA = tR < 9 ? tR : 9;          // register indices per sub-round
+    static constexpr int NSUB = (tR + S_GA - 1) / S_GA;
+    static constexpr int Q = (S_GA + tW - 1) / tW;        // register indices per wave per sub-round
+    static constexpr int LDS = mW == 0 ? 0 : 2 * tW * S_GA * 64;  // elements
+};
+
+// One tile of an inverse pass.  `wave` must be wave-uniform; waves with
+// wave >= PassCfg::WAVES take part in the barriers only.  S holds
+// PassCfg::LDS elements when mW > 0.  EXACT: the workgroup has exactly
+// PassCfg::WAVES waves and, when mW > 0, every wave is known to be active.
+template <typename T, int mR, int mW, int CW, bool ADJ, bool EXACT = false>
+__device__ __forceinline__ void inv_tile(const T* src, T* dst, uint64_t L, uint32_t hi, uint32_t j, bool in_place,
+                                         int wave, T* S)
 {
-    constexpr int tA = pow3c(mA), tB = pow3c(mB), TM = tA * tB;
-    z += (uint64_t)blockIdx.y * z_bstride;
-    const int tid = threadIdx.x;
-    const TileWalk w = xcd_tile_walk(n_tiles);
-    if constexpr (mB == 0) {
-        for (uint32_t t = w.first; t < w.end; t += w.step) {
-            const uint32_t hi = t / tiles_per_hi;
-            const uint32_t j = t - hi * tiles_per_hi;
-            const uint64_t lo = (uint64_t)j * NT + tid;
-            if (lo < L) {
-                T* base = z + (uint64_t)hi * TM * L + lo;
-                T v[tA];
+    using P = PassCfg<mR, mW, CW>;
+    constexpr int tR = P::tR, tW = P::tW, TM = tR * tW;
+    constexpr int tInner = ADJ ? tW : tR;  // rows per step of the group's outer part
+    const int lane = threadIdx.x & 63;
+    const int cg = wave / tW;
+    const int gW1 = wave - cg * tW;
+    const uint64_t lo_w = (uint64_t)j * P::COLS + (uint64_t)cg * 64;  // this wave's first column
+    // with a wave part the tile's first column lo_w = j * 64 is always < L
+    const bool active = (EXACT && mW > 0) ? true : (wave < P::WAVES && lo_w < L);
+    const uint32_t col = (lo_w + lane < L) ? lane : 0;
+    const uint32_t col_off = col * (uint32_t)sizeof(T);
+    const uint64_t row_bytes = L * sizeof(T);
+    const uint64_t tile_off = ((uint64_t)hi * TM * L + lo_w) * sizeof(T);
+    const char* s_tile = reinterpret_cast<const char*>(src) + tile_off;
+    char* d_tile = reinterpret_cast<char*>(dst) + tile_off;
+    T v[tR];
+    if (active) {
+        // phase 1: rows wave*tR + gR (forward) or gR*tW + wave (adjoint)
+        const uint64_t step = (ADJ ? (uint64_t)tInner : 1ull) * row_bytes;
+        const char* rp = s_tile + (uint64_t)(ADJ ? gW1 : gW1 * tInner) * row_bytes;
 #pragma unroll
-                for (int g = 0; g < tA; ++g) v[g] = base[(uint64_t)g * L];
-                inv_group<T, mA>(v);
+        for (int gR = 0; gR < tR; ++gR) {
+            v[gR] = *reinterpret_cast<const T*>(rp + col_off);
+            rp += step;
+        }
+        if constexpr (ADJ) inv_adj_group<T, mR>(v);
+        else inv_group<T, mR>(v);
+        if constexpr (mW == 0) {
+            char* wp = d_tile;
 #pragma unroll
-                for (int g = 0; g < tA; ++g)
-                    if (has_digit_one(g, mA)) base[(uint64_t)g * L] = v[g];
+            for (int gR = 0; gR < tR; ++gR) {
+                const bool changed = ADJ ? !all_digits_one(gR, mR) : has_digit_one(gR, mR);
+                if (changed || !in_place) *reinterpret_cast<T*>(wp + col_off) = v[gR];
+                wp += row_bytes;
             }
         }
-    } else {
-        __shared__ T S[TM * C];
-        for (uint32_t t = w.first; t < w.end; t += w.step) {
-            const uint32_t hi = t / tiles_per_hi;
-            const uint32_t j = t - hi * tiles_per_hi;
-            const uint64_t lo0 = (uint64_t)j * C;
-            T* base = z + (uint64_t)hi * TM * L + lo0;
-            lds_barrier();
-            for (int it = tid; it < tB * C; it += NT) {
-                const int gB = it / C;
-                const int cl = it - gB * C;
-                const bool ok = lo0 + cl < L;
-                T v[tA];
+    }
+    if constexpr (mW > 0) {
+        // S viewed as [2][tW][S_GA][64]
 #pragma unroll
-                for (int gA = 0; gA < tA; ++gA)
-                    v[gA] = ok ? base[(uint64_t)(gB * tA + gA) * L + cl] : T(0);
-                inv_group<T, mA>(v);
+        for (int r = 0; r < P::NSUB; ++r) {
+            T* Sb = S + (r & 1) * (tW * P::S_GA * 64);
+            if (active) {
 #pragma unroll
-                for (int gA = 0; gA < tA; ++gA) S[(gB * tA + gA) * C + cl] = v[gA];
+                for (int k = 0; k < P::S_GA; ++k)
+                    if (r * P::S_GA + k < tR) Sb[(gW1 * P::S_GA + k) * 64 + lane] = v[r * P::S_GA + k];
             }
             lds_barrier();
-            for (int it = tid; it < tA * C; it += NT) {
-                const int gA = it / C;
-                const int cl = it - gA * C;
-                if (lo0 + cl < L) {
-                    T v[tB];
 #pragma unroll
-                    for (int gB = 0; gB < tB; ++gB) v[gB] = S[(gB * tA + gA) * C + cl];
-                    inv_group<T, mB>(v);
-                    bool a_one = false;
-                    int g = gA;
+            for (int q = 0; q < P::Q; ++q) {
+                const int k = gW1 * P::Q + q;
+                const int gR = r * P::S_GA + k;
+                if (active && k < P::S_GA && gR < tR) {
+                    T u[tW];
 #pragma unroll
-                    for (int d = 0; d < mA; ++d) {
-                        a_one |= (g % 3 == 1);
+                    for (int gW = 0; gW < tW; ++gW) u[gW] = Sb[(gW * P::S_GA + k) * 64 + lane];
+                    if constexpr (ADJ) inv_adj_group<T, mW>(u);
+                    else inv_group<T, mW>(u);
+                    // G: some digit of gR is 1; G^T: every digit of gR is 1
+                    bool r_flag = ADJ;
+                    int g = gR;
+#pragma unroll
+                    for (int d = 0; d < mR; ++d) {
+                        if (ADJ) r_flag = r_flag && (g % 3 == 1);
+                        else r_flag = r_flag || (g % 3 == 1);
                         g /= 3;
                     }
+                    // forward: rows gW*tR + gR; adjoint: rows gR*tW + gW
+                    const uint64_t step = (ADJ ? 1ull : (uint64_t)tInner) * row_bytes;
+                    char* wp = d_tile + (uint64_t)(ADJ ? gR * tInner : gR) * row_bytes;
 #pragma unroll
-                    for (int gB = 0; gB < tB; ++gB)
-                        if (has_digit_one(gB, mB) || a_one) base[(uint64_t)(gB * tA + gA) * L + cl] = v[gB];
+                    for (int gW = 0; gW < tW; ++gW) {
+                        const bool changed = ADJ ? !(r_flag && all_digits_one(gW, mW))
+                                                 : (r_flag || has_digit_one(gW, mW));
+                        if (changed || !in_place) *reinterpret_cast<T*>(wp + col_off) = u[gW];
+                        wp += step;
+                    }
                 }
             }
         }
     }
 }
 
-// =========================================================================
-// Backward: G^T on m = mB + mA consecutive axes (ascending: group B, the
-// group's outer axes, first).  src -> dst, which may be the same buffer.
-//   mB == 0:  one thread per column.
-//   mB >  0:  phase 1 thread per (gA, column) does G^T on B, parks in LDS;
-//             phase 2 thread per (gB, column) does G^T on A and stores.
-// Entries whose group digits are all 1 are unchanged by G^T; in place they
-// are not written back.
-// =========================================================================
-template <typename T, int mA, int mB, int C, int NT>
-__global__ __launch_bounds__(NT) void k_inv_adj_pass(const T* src, T* dst, uint64_t src_bstride,
-                                                     uint64_t dst_bstride, uint64_t L,
-                                                     uint32_t tiles_per_hi, uint32_t n_tiles)
+template <typename T, int mR, int mW, int CW, bool ADJ>
+__global__ __launch_bounds__(64 * pow3c(mW) * CW) void k_inv_pass(const T* src, T* dst, uint64_t src_bstride,
+                                                                 uint64_t dst_bstride, uint64_t L,
+                                                                 uint32_t tiles_per_hi, uint32_t n_tiles)
 {
-    constexpr int tA = pow3c(mA), tB = pow3c(mB), TM = tA * tB;
+    using P = PassCfg<mR, mW, CW>;
+    __shared__ T S[P::LDS > 0 ? P::LDS : 1];
     src += (uint64_t)blockIdx.y * src_bstride;
     dst += (uint64_t)blockIdx.y * dst_bstride;
     const bool in_place = (src == dst);
-    const int tid = threadIdx.x;
-    const TileWalk w = xcd_tile_walk(n_tiles);
-    if constexpr (mB == 0) {
-        for (uint32_t t = w.first; t < w.end; t += w.step) {
-            const uint32_t hi = t / tiles_per_hi;
-            const uint32_t j = t - hi * tiles_per_hi;
-            const uint64_t lo = (uint64_t)j * NT + tid;
-            if (lo < L) {
-                const uint64_t off = (uint64_t)hi * TM * L + lo;
-                T v[tA];
-#pragma unroll
-                for (int g = 0; g < tA; ++g) v[g] = src[off + (uint64_t)g * L];
-                inv_adj_group<T, mA>(v);
-#pragma unroll
-                for (int g = 0; g < tA; ++g)
-                    if (!in_place || !all_digits_one(g, mA)) dst[off + (uint64_t)g * L] = v[g];
-            }
-        }
-    } else {
-        __shared__ T S[TM * C];
-        for (uint32_t t = w.first; t < w.end; t += w.step) {
-            const uint32_t hi = t / tiles_per_hi;
-            const uint32_t j = t - hi * tiles_per_hi;
-            const uint64_t lo0 = (uint64_t)j * C;
-            const uint64_t off = (uint64_t)hi * TM * L + lo0;
-            lds_barrier();
-            for (int it = tid; it < tA * C; it += NT) {
-                const int gA = it / C;
-                const int cl = it - gA * C;
-                const bool ok = lo0 + cl < L;
-                T v[tB];
-#pragma unroll
-                for (int gB = 0; gB < tB; ++gB)
-                    v[gB] = ok ? src[off + (uint64_t)(gB * tA + gA) * L + cl] : T(0);
-                inv_adj_group<T, mB>(v);
-#pragma unroll
-                for (int gB = 0; gB < tB; ++gB) S[(gB * tA + gA) * C + cl] = v[gB];
-            }
-            lds_barrier();
-            for (int it = tid; it < tB * C; it += NT) {
-                const int gB = it / C;
-                const int cl = it - gB * C;
-                if (lo0 + cl < L) {
-                    T v[tA];
-#pragma unroll
-                    for (int gA = 0; gA < tA; ++gA) v[gA] = S[(gB * tA + gA) * C + cl];
-                    inv_adj_group<T, mA>(v);
-                    bool b_all_one = true;
-                    int g = gB;
-#pragma unroll
-                    for (int d = 0; d < mB; ++d) {
-                        b_all_one &= (g % 3 == 1);
-                        g /= 3;
-                    }
-#pragma unroll
-                    for (int gA = 0; gA < tA; ++gA)
-                        if (!in_place || !(b_all_one && all_digits_one(gA, mA)))
-                            dst[off + (uint64_t)(gB * tA + gA) * L + cl] = v[gA];
-                }
-            }
-        }
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const TileWalk walk = xcd_tile_walk(n_tiles);
+    for (uint32_t t = walk.first; t < walk.end; t += walk.step) {
+        const uint32_t hi = t / tiles_per_hi;
+        const uint32_t j = t - hi * tiles_per_hi;
+        if constexpr (mW > 0) lds_barrier();  // the previous tile's phase-2 reads are done
+        inv_tile<T, mR, mW, CW, ADJ, true>(src, dst, L, hi, j, in_place, wave, S);
     }
 }
 
 // =========================================================================
 // Backward: F^T on M consecutive axes (descending), out of place.
 //   in [n_hi][3^M][L]  ->  out [n_hi][2^M][L],   L = 2^log2L
-// blockIdx.y = batch item, blockIdx.z = operand.
 // =========================================================================
-template <typename T, int M, int NT>
-__global__ __launch_bounds__(NT) void k_fwd_adj_pass(const T* __restrict__ in0, const T* __restrict__ in1,
-                                                     T* __restrict__ out0, T* __restrict__ out1,
-                                                     uint64_t in_bstride, uint64_t out_bstride,
-                                                     uint32_t n_cols, uint32_t log2L)
+template <typename T, int M>
+__device__ __forceinline__ void fwd_adj_column(const T* __restrict__ in, T* __restrict__ out, uint32_t c,
+                                               uint32_t log2L)
 {
-    const T* in = blockIdx.z ? in1 : in0;
-    T* out = blockIdx.z ? out1 : out0;
-    if (out == nullptr) return;
-    in += (uint64_t)blockIdx.y * in_bstride;
-    out += (uint64_t)blockIdx.y * out_bstride;
-    const uint32_t c = blockIdx.x * NT + threadIdx.x;
-    if (c >= n_cols) return;
     const uint64_t L = 1ull << log2L;
     const uint64_t hi = c >> log2L;
     const uint64_t lo = c & (L - 1);
@@ -403,6 +397,22 @@ __global__ __launch_bounds__(NT) void k_fwd_adj_pass(const T* __restrict__ in0, 
     for (int b = 0; b < (1 << M); ++b) dst[(uint64_t)b * L] = s[b];
 }
 
+// blockIdx.y = batch item, blockIdx.z = operand; a null output skips it.
+template <typename T, int M, int NT>
+__global__ __launch_bounds__(NT) void k_fwd_adj_pass(const T* __restrict__ in0, const T* __restrict__ in1,
+                                                     T* __restrict__ out0, T* __restrict__ out1,
+                                                     uint64_t in_bstride, uint64_t out_bstride,
+                                                     uint32_t n_cols, uint32_t log2L)
+{
+    const T* in = blockIdx.z ? in1 : in0;
+    T* out = blockIdx.z ? out1 : out0;
+    if (out == nullptr) return;
+    const uint32_t c = blockIdx.x * NT + threadIdx.x;
+    if (c >= n_cols) return;
+    fwd_adj_column<T, M>(in + (uint64_t)blockIdx.y * in_bstride, out + (uint64_t)blockIdx.y * out_bstride, c,
+                         log2L);
+}
+
 // =========================================================================
 // Fused inner tile of the backward pass, for one outer index o:
 //   Q0  x~[o], y~[o] -> F on groups C, B (shared with the forward)      -> R2
@@ -413,8 +423,125 @@ __global__ __launch_bounds__(NT) void k_fwd_adj_pass(const T* __restrict__ in0, 
 //   Q4  F^T on group B (thread per (gC, bA))                          R2 -> R1
 //   Q5  F^T on group C (thread per (bB, bA)), contiguous store of the
 //       2^K-entry rows gx~[o], gy~[o]
-// Either gradient output may be null (not requested).
+// Either gradient row may be null (not requested).  lds holds
+// FusedCfg<K>::ADJ_LDS elements.
 // =========================================================================
+template <typename T, int K, int NT>
+__device__ __forceinline__ void fused_tile_adj(const T* __restrict__ xr, const T* __restrict__ yr,
+                                               const T* __restrict__ wr, T* __restrict__ gxr,
+                                               T* __restrict__ gyr, T* lds)
+{
+    using C = FusedCfg<K>;
+    T* R2 = lds;                       // x2, y2, later gx2, gy2
+    T* U = lds + 2 * C::R2h;           // R0 + R1 during Q0, W from Q1, R1' in Q4
+    T* R0 = U;
+    T* R1 = U + 2 * C::R0h;
+    T* W = U;
+    constexpr int N3I = C::tC * C::tB;
+    constexpr int IPT = (N3I + NT - 1) / NT;
+    const int tid = threadIdx.x;
+    fused_forward_cb<T, K, NT>(xr, yr, R0, R1, R2);
+    // Q1: G^T on group C, straight from global memory
+    for (int it = tid; it < C::tB * C::tA; it += NT) {
+        T v[pow3c(C::kC)];
+#pragma unroll
+        for (int gC = 0; gC < C::tC; ++gC) v[gC] = wr[gC * (C::tB * C::tA) + it];
+        inv_adj_group<T, C::kC>(v);
+#pragma unroll
+        for (int gC = 0; gC < C::tC; ++gC) W[gC * (C::tB * C::tA) + it] = v[gC];
+    }
+    lds_barrier();
+    // Q2: G^T on group B
+    if constexpr (C::kB > 0) {
+        for (int it = tid; it < C::tC * C::tA; it += NT) {
+            const int gC = it / C::tA;
+            const int gA = it - gC * C::tA;
+            T v[pow3c(C::kB)];
+#pragma unroll
+            for (int gB = 0; gB < C::tB; ++gB) v[gB] = W[(gC * C::tB + gB) * C::tA + gA];
+            inv_adj_group<T, C::kB>(v);
+#pragma unroll
+            for (int gB = 0; gB < C::tB; ++gB)
+                if (!all_digits_one(gB, C::kB)) W[(gC * C::tB + gB) * C::tA + gA] = v[gB];
+        }
+        lds_barrier();
+    }
+    // Q3: registers take this thread's W row and R2 columns; then R2 is reused
+    T wa[IPT][pow3c(C::kA)], xa[IPT][C::nA], ya[IPT][C::nA];
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) {
+        const int it = tid + j * NT;
+        if (it < N3I) {
+#pragma unroll
+            for (int g = 0; g < C::tA; ++g) wa[j][g] = W[it * C::tA + g];
+#pragma unroll
+            for (int bA = 0; bA < C::nA; ++bA) {
+                xa[j][bA] = R2[bA * N3I + it];
+                ya[j][bA] = R2[C::R2h + bA * N3I + it];
+            }
+        }
+    }
+    lds_barrier();
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) {
+        const int it = tid + j * NT;
+        if (it < N3I) {
+            inv_adj_group<T, C::kA>(wa[j]);
+            if (gyr) {
+                T s[pow3c(C::kA)];
+#pragma unroll
+                for (int bA = 0; bA < C::nA; ++bA) s[bA] = xa[j][bA];
+                fwd_group<T, C::kA>(s);
+#pragma unroll
+                for (int g = 0; g < C::tA; ++g) s[g] = wa[j][g] * s[g];
+                fwd_adj_group<T, C::kA>(s);
+#pragma unroll
+                for (int bA = 0; bA < C::nA; ++bA) R2[C::R2h + bA * N3I + it] = s[bA];
+            }
+            if (gxr) {
+                T s[pow3c(C::kA)];
+#pragma unroll
+                for (int bA = 0; bA < C::nA; ++bA) s[bA] = ya[j][bA];
+                fwd_group<T, C::kA>(s);
+#pragma unroll
+                for (int g = 0; g < C::tA; ++g) s[g] = wa[j][g] * s[g];
+                fwd_adj_group<T, C::kA>(s);
+#pragma unroll
+                for (int bA = 0; bA < C::nA; ++bA) R2[bA * N3I + it] = s[bA];
+            }
+        }
+    }
+    lds_barrier();
+    // Q4: F^T on group B: R2 [bA][gC][gB] -> R1 [gC][bB][bA]
+    for (int it = tid; it < 2 * C::tC * C::nA; it += NT) {
+        const int op = it / (C::tC * C::nA);
+        if ((op == 0 && !gxr) || (op == 1 && !gyr)) continue;
+        const int r = it - op * (C::tC * C::nA);
+        const int gC = r / C::nA;
+        const int bA = r - gC * C::nA;
+        T s[pow3c(C::kB)];
+#pragma unroll
+        for (int gB = 0; gB < C::tB; ++gB) s[gB] = R2[op * C::R2h + (bA * C::tC + gC) * C::tB + gB];
+        fwd_adj_group<T, C::kB>(s);
+#pragma unroll
+        for (int bB = 0; bB < C::nB; ++bB) R1[op * C::R1h + (gC * C::nB + bB) * C::nA + bA] = s[bB];
+    }
+    lds_barrier();
+    // Q5: F^T on group C and the contiguous stores of the two rows
+    for (int it = tid; it < 2 * C::nB * C::nA; it += NT) {
+        const int op = it / (C::nB * C::nA);
+        T* g = op == 0 ? gxr : gyr;
+        if (!g) continue;
+        const int r = it - op * (C::nB * C::nA);
+        T s[pow3c(C::kC)];
+#pragma unroll
+        for (int gC = 0; gC < C::tC; ++gC) s[gC] = R1[op * C::R1h + gC * (C::nB * C::nA) + r];
+        fwd_adj_group<T, C::kC>(s);
+#pragma unroll
+        for (int bC = 0; bC < C::nC; ++bC) g[bC * (C::nB * C::nA) + r] = s[bC];
+    }
+}
+
 template <typename T, int K, int NT>
 __global__ __launch_bounds__(NT) void k_fused_inner_adj(const T* __restrict__ xt, const T* __restrict__ yt,
                                                         const T* __restrict__ w, T* __restrict__ gxt,
@@ -424,125 +551,17 @@ __global__ __launch_bounds__(NT) void k_fused_inner_adj(const T* __restrict__ xt
 {
     using C = FusedCfg<K>;
     __shared__ T lds[C::ADJ_LDS];
-    T* R2 = lds;                       // x2, y2, later gx2, gy2
-    T* U = lds + 2 * C::R2h;           // R0 + R1 during Q0, W from Q1, R1' in Q4
-    T* R0 = U;
-    T* R1 = U + 2 * C::R0h;
-    T* W = U;
-    constexpr int N3I = C::tC * C::tB;
-    constexpr int IPT = (N3I + NT - 1) / NT;
-    const int tid = threadIdx.x;
     xt += (uint64_t)blockIdx.y * in_bstride;
     yt += (uint64_t)blockIdx.y * in_bstride;
     w += (uint64_t)blockIdx.y * w_bstride;
     if (gxt) gxt += (uint64_t)blockIdx.y * g_bstride;
     if (gyt) gyt += (uint64_t)blockIdx.y * g_bstride;
-
     const TileWalk walk = xcd_tile_walk(n_tiles);
     for (uint32_t o = walk.first; o < walk.end; o += walk.step) {
         lds_barrier();
-        fused_forward_cb<T, K, NT>(xt + (uint64_t)o * C::N2, yt + (uint64_t)o * C::N2, R0, R1, R2);
-        // Q1: G^T on group C, straight from global memory
-        const T* wr = w + (uint64_t)o * C::N3;
-        for (int it = tid; it < C::tB * C::tA; it += NT) {
-            T v[pow3c(C::kC)];
-#pragma unroll
-            for (int gC = 0; gC < C::tC; ++gC) v[gC] = wr[gC * (C::tB * C::tA) + it];
-            inv_adj_group<T, C::kC>(v);
-#pragma unroll
-            for (int gC = 0; gC < C::tC; ++gC) W[gC * (C::tB * C::tA) + it] = v[gC];
-        }
-        lds_barrier();
-        // Q2: G^T on group B
-        if constexpr (C::kB > 0) {
-            for (int it = tid; it < C::tC * C::tA; it += NT) {
-                const int gC = it / C::tA;
-                const int gA = it - gC * C::tA;
-                T v[pow3c(C::kB)];
-#pragma unroll
-                for (int gB = 0; gB < C::tB; ++gB) v[gB] = W[(gC * C::tB + gB) * C::tA + gA];
-                inv_adj_group<T, C::kB>(v);
-#pragma unroll
-                for (int gB = 0; gB < C::tB; ++gB)
-                    if (!all_digits_one(gB, C::kB)) W[(gC * C::tB + gB) * C::tA + gA] = v[gB];
-            }
-            lds_barrier();
-        }
-        // Q3: registers take this thread's W row and R2 columns; then R2 is reused
-        T wa[IPT][pow3c(C::kA)], xa[IPT][C::nA], ya[IPT][C::nA];
-#pragma unroll
-        for (int j = 0; j < IPT; ++j) {
-            const int it = tid + j * NT;
-            if (it < N3I) {
-#pragma unroll
-                for (int g = 0; g < C::tA; ++g) wa[j][g] = W[it * C::tA + g];
-#pragma unroll
-                for (int bA = 0; bA < C::nA; ++bA) {
-                    xa[j][bA] = R2[bA * N3I + it];
-                    ya[j][bA] = R2[C::R2h + bA * N3I + it];
-                }
-            }
-        }
-        lds_barrier();
-#pragma unroll
-        for (int j = 0; j < IPT; ++j) {
-            const int it = tid + j * NT;
-            if (it < N3I) {
-                inv_adj_group<T, C::kA>(wa[j]);
-                if (gyt) {
-                    T s[pow3c(C::kA)];
-#pragma unroll
-                    for (int bA = 0; bA < C::nA; ++bA) s[bA] = xa[j][bA];
-                    fwd_group<T, C::kA>(s);
-#pragma unroll
-                    for (int g = 0; g < C::tA; ++g) s[g] = wa[j][g] * s[g];
-                    fwd_adj_group<T, C::kA>(s);
-#pragma unroll
-                    for (int bA = 0; bA < C::nA; ++bA) R2[C::R2h + bA * N3I + it] = s[bA];
-                }
-                if (gxt) {
-                    T s[pow3c(C::kA)];
-#pragma unroll
-                    for (int bA = 0; bA < C::nA; ++bA) s[bA] = ya[j][bA];
-                    fwd_group<T, C::kA>(s);
-#pragma unroll
-                    for (int g = 0; g < C::tA; ++g) s[g] = wa[j][g] * s[g];
-                    fwd_adj_group<T, C::kA>(s);
-#pragma unroll
-                    for (int bA = 0; bA < C::nA; ++bA) R2[bA * N3I + it] = s[bA];
-                }
-            }
-        }
-        lds_barrier();
-        // Q4: F^T on group B: R2 [bA][gC][gB] -> R1 [gC][bB][bA]
-        for (int it = tid; it < 2 * C::tC * C::nA; it += NT) {
-            const int op = it / (C::tC * C::nA);
-            if ((op == 0 && !gxt) || (op == 1 && !gyt)) continue;
-            const int r = it - op * (C::tC * C::nA);
-            const int gC = r / C::nA;
-            const int bA = r - gC * C::nA;
-            T s[pow3c(C::kB)];
-#pragma unroll
-            for (int gB = 0; gB < C::tB; ++gB) s[gB] = R2[op * C::R2h + (bA * C::tC + gC) * C::tB + gB];
-            fwd_adj_group<T, C::kB>(s);
-#pragma unroll
-            for (int bB = 0; bB < C::nB; ++bB) R1[op * C::R1h + (gC * C::nB + bB) * C::nA + bA] = s[bB];
-        }
-        lds_barrier();
-        // Q5: F^T on group C and the contiguous stores of the two rows
-        for (int it = tid; it < 2 * C::nB * C::nA; it += NT) {
-            const int op = it / (C::nB * C::nA);
-            T* g = op == 0 ? gxt : gyt;
-            if (!g) continue;
-            const int r = it - op * (C::nB * C::nA);
-            T s[pow3c(C::kC)];
-#pragma unroll
-            for (int gC = 0; gC < C::tC; ++gC) s[gC] = R1[op * C::R1h + gC * (C::nB * C::nA) + r];
-            fwd_adj_group<T, C::kC>(s);
-            T* gr = g + (uint64_t)o * C::N2;
-#pragma unroll
-            for (int bC = 0; bC < C::nC; ++bC) gr[bC * (C::nB * C::nA) + r] = s[bC];
-        }
+        fused_tile_adj<T, K, NT>(xt + (uint64_t)o * C::N2, yt + (uint64_t)o * C::N2, w + (uint64_t)o * C::N3,
+                                 gxt ? gxt + (uint64_t)o * C::N2 : nullptr,
+                                 gyt ? gyt + (uint64_t)o * C::N2 : nullptr, lds);
     }
 }
 

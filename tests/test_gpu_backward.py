@@ -37,7 +37,8 @@ def test_backward_matches_oracle(dtype, D):
 
 
 @pytest.mark.parametrize("plan", [dict(HC_FUSED_K="2"), dict(HC_FUSED_K="5"), dict(HC_INV_MAXM="2"),
-                                  dict(HC_INV_MAXM="4"), dict(HC_INV_MAXM="5")])
+                                  dict(HC_INV_MAXM="4"), dict(HC_INV_MAXM="5"), dict(HC_INV_REG="1"),
+                                  dict(HC_INV_REG="2"), dict(HC_INV_REG="3"), dict(HC_GRID_PER_CU="2")])
 def test_backward_every_plan_identical(plan, monkeypatch):
     for k, v in plan.items():
         monkeypatch.setenv(k, v)

@@ -67,8 +67,9 @@ def test_int64_matches_algorithm1(D):
 @pytest.mark.parametrize("plan", [
     dict(HC_FUSED_K="1"), dict(HC_FUSED_K="3"), dict(HC_FUSED_K="5"), dict(HC_FUSED_K="7"),
     dict(HC_INV_MAXM="1"), dict(HC_INV_MAXM="2"), dict(HC_INV_MAXM="3"), dict(HC_INV_MAXM="4"),
-    dict(HC_INV_MAXM="5"), dict(HC_INV_MAXM="6", HC_INV_COLS="8"),
-    dict(HC_FUSED_K="4", HC_INV_MAXM="5", HC_INV_COLS="8"),
+    dict(HC_INV_MAXM="5"), dict(HC_INV_REG="1"), dict(HC_INV_REG="2"), dict(HC_INV_REG="3"),
+    dict(HC_FUSED_K="4", HC_INV_MAXM="5", HC_INV_REG="3"), dict(HC_GRID_PER_CU="2"),
+    dict(HC_FUSED_K="2", HC_GRID_PER_CU="1", HC_INV_REG="2"),
 ])
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
 def test_every_plan_gives_identical_bits(plan, dtype, monkeypatch):
