@@ -157,6 +157,78 @@ int hc_convolve_backward(const void* x, const void* y, const void* grad_z,
                          void* workspace, size_t workspace_bytes, hipStream_t stream);
 
 /*
+ * Batched plans: many independent pairs of uneven D in one graph launch.
+ *
+ * The pairs are packed: pair i's x (and y) occupy 2^D_i elements at element
+ * offset x_off[i] = sum_{j<i} 2^D_j, and its z occupies 3^D_i elements at
+ * z_off[i] = sum_{j<i} 3^D_j (hc_plan_layout returns both arrays).
+ *
+ * A plan groups the pairs by D; each group runs the single-pair path for all
+ * its items at once (outer forward passes, fused inner tiles, outer inverse
+ * passes), reading and writing every item in place in the packed buffers.
+ * The groups are independent branches of one HIP graph, captured on the
+ * first execution (and again whenever the buffers change) and replayed.
+ * Results are bitwise those of hc_convolve on each pair.
+ */
+typedef struct hc_plan hc_plan;
+
+/* Plan flags */
+#define HC_PLAN_TUNE 1u        /* time candidate schedules per D at creation, keep the fastest */
+#define HC_PLAN_PERSISTENT 2u  /* one persistent kernel for all pairs: disabled, returns HC_ERR_UNSUPPORTED */
+
+/*
+ * Create a plan for n_pairs pairs with dimensions Ds[0..n_pairs) (host
+ * array, 0 <= D <= 16) of `dtype`.  Allocates the plan's device tables and
+ * streams on the current device.  With HC_PLAN_TUNE it also allocates
+ * temporary buffers and times candidate schedules (this synchronises the
+ * device); with the environment variable HC_TUNE_CACHE naming a file, tuned
+ * choices are read from and appended to that file.
+ * Errors: HC_ERR_INVALID_ARG (null Ds/out, n_pairs < 1, unknown flag),
+ * HC_ERR_D_RANGE, HC_ERR_UNSUPPORTED, HC_ERR_NO_DEVICE, HC_ERR_HIP.
+ */
+int hc_plan_create_batched(const int* Ds, int n_pairs, int dtype, unsigned flags, hc_plan** out);
+
+/* Release the plan's device tables, streams and graph.  NULL is ignored. */
+int hc_plan_destroy(hc_plan* plan);
+
+/* Workspace bytes hc_plan_execute needs ((size_t)-1 for a null plan). */
+size_t hc_plan_workspace_bytes(const hc_plan* plan);
+
+/*
+ * Packed layout: x_offsets and z_offsets (host arrays of n_pairs + 1
+ * elements, either may be NULL) receive the element offsets of every pair
+ * and, last, the total element counts.
+ */
+int hc_plan_layout(const hc_plan* plan, uint64_t* x_offsets, uint64_t* z_offsets);
+
+/*
+ * Run the plan: z = x * y for every pair of the packed buffers.  x, y, z and
+ * the workspace follow the conventions above (device, 16-byte aligned, z
+ * disjoint from the others).  Enqueued on `stream` as one graph launch.
+ * Errors: HC_ERR_INVALID_ARG, HC_ERR_ALIAS, HC_ERR_MISALIGNED,
+ * HC_ERR_WORKSPACE, HC_ERR_HIP.
+ */
+int hc_plan_execute(hc_plan* plan, const void* x, const void* y, void* z, void* workspace,
+                    size_t workspace_bytes, hipStream_t stream);
+
+/* Synchronise the device and report any asynchronous error: HC_OK or HC_ERR_HIP. */
+int hc_plan_check(hc_plan* plan);
+
+/* JSON description of the plan's schedule (groups, fused depth, inverse groups). */
+int hc_plan_describe(const hc_plan* plan, char* buf, size_t len);
+
+/*
+ * Host-only view of the groups a plan for these pairs would use with the
+ * default schedule (no device needed; HC_PLAN_TUNE is ignored).  For each
+ * group `info` receives 6 values: D, number of pairs, first pair index,
+ * fused depth K, number of outer forward passes, number of outer inverse
+ * passes; at most `capacity` groups are written and *n_groups receives the
+ * total.  Errors as hc_plan_create_batched for the arguments.
+ */
+int hc_plan_inspect(const int* Ds, int n_pairs, int dtype, unsigned flags, int64_t* info, int64_t capacity,
+                    int64_t* n_groups);
+
+/*
  * Kernel profiler (measurement support; not part of the method).
  * While enabled, every kernel launch of the calling process is bracketed by
  * a pair of HIP events recorded on the launch stream, and tagged with the

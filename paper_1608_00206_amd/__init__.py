@@ -24,7 +24,7 @@ import torch
 from . import _abi
 from ._abi import HCError
 
-__all__ = ["convolve", "convolve_batch", "convolve_backward", "HypercubeConv", "HCError",
+__all__ = ["convolve", "convolve_batch", "convolve_backward", "HypercubeConv", "HCError", "BatchedPlan",
            "workspace_bytes", "backward_workspace_bytes", "dim_of", "DTYPES"]
 
 DTYPES = {torch.float64: _abi.HC_F64, torch.float32: _abi.HC_F32, torch.int64: _abi.HC_I64}
@@ -187,3 +187,78 @@ class HypercubeConv(torch.autograd.Function):
             gx = gx.squeeze(0) if gx is not None else None
             gy = gy.squeeze(0) if gy is not None else None
         return gx, gy
+
+
+class BatchedPlan:
+    """Many independent pairs of uneven D in one launch of a HIP graph
+    (hc_plan_* in include/hc.h): pairs grouped by D, each group one batched
+    run of the single-pair kernels, the groups parallel graph branches.
+
+    Ds: the pairs' dimensions (0..16).  Inputs are packed: pair i's x and y
+    occupy x_offsets[i]:x_offsets[i+1] of x_packed / y_packed, its z occupies
+    z_offsets[i]:z_offsets[i+1] of the output.
+    tune=True times candidate schedules per D at creation and keeps the
+    fastest; persistent=True asks for the single persistent kernel, which is
+    disabled (HCError HC_ERR_UNSUPPORTED).
+    """
+
+    def __init__(self, Ds, dtype: torch.dtype = torch.float64, tune: bool = False, persistent: bool = False):
+        import json
+        self._h = None
+        self.Ds = [int(d) for d in Ds]
+        self.dtype = dtype
+        flags = (_abi.HC_PLAN_TUNE if tune else 0) | (_abi.HC_PLAN_PERSISTENT if persistent else 0)
+        self._h = _abi.hc_plan_create_batched(self.Ds, DTYPES[dtype], flags)
+        self.x_offsets, self.z_offsets = _abi.hc_plan_layout(self._h, len(self.Ds))
+        self.workspace_bytes = _abi.hc_plan_workspace_bytes(self._h)
+        self.schedule = json.loads(_abi.hc_plan_describe(self._h))
+
+    @property
+    def n_inputs(self) -> int:
+        return self.x_offsets[-1]
+
+    @property
+    def n_outputs(self) -> int:
+        return self.z_offsets[-1]
+
+    def run(self, x: torch.Tensor, y: torch.Tensor, out: torch.Tensor | None = None,
+            workspace: torch.Tensor | None = None) -> torch.Tensor:
+        if self._h is None:
+            raise RuntimeError("plan closed")
+        if x.dtype != self.dtype or y.dtype != self.dtype:
+            raise TypeError("inputs must have the plan's dtype")
+        if x.numel() != self.n_inputs or y.numel() != self.n_inputs:
+            raise ValueError(f"packed inputs must have {self.n_inputs} elements")
+        _check_device(x, y)
+        x = x.contiguous()
+        y = y.contiguous()
+        if out is None:
+            out = torch.empty(self.n_outputs, dtype=self.dtype, device=x.device)
+        elif out.numel() != self.n_outputs or out.dtype != self.dtype or not out.is_contiguous():
+            raise ValueError("out must be a contiguous tensor of n_outputs elements")
+        ws = _workspace(self.workspace_bytes, x.device, workspace)
+        _abi.check(_abi.hc_plan_execute(self._h, x.data_ptr(), y.data_ptr(), out.data_ptr(),
+                                        ws.data_ptr() if ws is not None else 0, self.workspace_bytes,
+                                        _stream(x.device)))
+        return out
+
+    def check(self) -> None:
+        """Synchronise and raise on an asynchronous device error."""
+        _abi.check(_abi.hc_plan_check(self._h))
+
+    def close(self) -> None:
+        if self._h is not None:
+            _abi.hc_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

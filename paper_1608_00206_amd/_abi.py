@@ -15,6 +15,7 @@ LIB_PATH = os.path.join(HERE, "libhc.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "hc.h")
 
 HC_F64, HC_F32, HC_I64 = 0, 1, 2
+HC_PLAN_TUNE, HC_PLAN_PERSISTENT = 1, 2
 HC_OK = 0
 STATUS_NAMES = {
     0: "HC_OK", 1: "HC_ERR_INVALID_ARG", 2: "HC_ERR_D_RANGE", 3: "HC_ERR_UNSUPPORTED",
@@ -56,6 +57,15 @@ SIGNATURES = {
     "hc_backward_workspace_bytes": ([_I, _I, _I], _SZ),
     "hc_convolve_backward_batch": ([_P, _P, _P, _I64, _P, _P, _I, _I, _I, _P, _SZ, _P], _I),
     "hc_convolve_backward": ([_P, _P, _P, _P, _P, _I, _I, _P, _SZ, _P], _I),
+    "hc_plan_create_batched": ([ctypes.POINTER(_I), _I, _I, ctypes.c_uint, ctypes.POINTER(_P)], _I),
+    "hc_plan_destroy": ([_P], _I),
+    "hc_plan_workspace_bytes": ([_P], _SZ),
+    "hc_plan_layout": ([_P, ctypes.POINTER(_U64), ctypes.POINTER(_U64)], _I),
+    "hc_plan_execute": ([_P, _P, _P, _P, _P, _SZ, _P], _I),
+    "hc_plan_check": ([_P], _I),
+    "hc_plan_describe": ([_P, ctypes.c_char_p, _SZ], _I),
+    "hc_plan_inspect": ([ctypes.POINTER(_I), _I, _I, ctypes.c_uint, ctypes.POINTER(_I64), _I64,
+                         ctypes.POINTER(_I64)], _I),
     "hc_profile_enable": ([_I], _I),
     "hc_profile_collect": ([ctypes.POINTER(KernelStat), _I, ctypes.POINTER(_I)], _I),
 }
@@ -142,3 +152,51 @@ def hc_profile_collect(capacity: int = 64):
     check(lib().hc_profile_collect(arr, capacity, ctypes.byref(n)))
     return [(arr[i].name.decode(), int(arr[i].launches), float(arr[i].total_ms), float(arr[i].alg_bytes))
             for i in range(n.value)]
+
+
+def hc_plan_create_batched(Ds, dtype: int, flags: int = 0) -> int:
+    """Returns the plan handle (an integer); raises HCError on failure."""
+    arr = (_I * len(Ds))(*[int(d) for d in Ds])
+    out = _P(0)
+    check(lib().hc_plan_create_batched(arr, len(Ds), dtype, flags, ctypes.byref(out)))
+    return out.value
+
+
+def hc_plan_destroy(plan: int) -> int:
+    return lib().hc_plan_destroy(plan)
+
+
+def hc_plan_workspace_bytes(plan: int) -> int:
+    return lib().hc_plan_workspace_bytes(plan)
+
+
+def hc_plan_layout(plan: int, n_pairs: int):
+    xo = (_U64 * (n_pairs + 1))()
+    zo = (_U64 * (n_pairs + 1))()
+    check(lib().hc_plan_layout(plan, xo, zo))
+    return list(xo), list(zo)
+
+
+def hc_plan_execute(plan: int, x: int, y: int, z: int, ws: int, ws_bytes: int, stream: int) -> int:
+    return lib().hc_plan_execute(plan, x, y, z, ws, ws_bytes, stream)
+
+
+def hc_plan_check(plan: int) -> int:
+    return lib().hc_plan_check(plan)
+
+
+def hc_plan_describe(plan: int) -> str:
+    buf = ctypes.create_string_buffer(1 << 16)
+    check(lib().hc_plan_describe(plan, buf, len(buf)))
+    return buf.value.decode()
+
+
+def hc_plan_inspect(Ds, dtype: int, flags: int = 0):
+    """Groups of the default schedule, host only: list of dicts."""
+    arr = (_I * len(Ds))(*[int(d) for d in Ds])
+    n = _I64(0)
+    check(lib().hc_plan_inspect(arr, len(Ds), dtype, flags, None, 0, ctypes.byref(n)))
+    info = (_I64 * (6 * n.value))()
+    check(lib().hc_plan_inspect(arr, len(Ds), dtype, flags, info, n.value, ctypes.byref(n)))
+    keys = ("D", "pairs", "first_pair", "K", "fwd_passes", "inv_passes")
+    return [dict(zip(keys, info[6 * i:6 * i + 6])) for i in range(n.value)]

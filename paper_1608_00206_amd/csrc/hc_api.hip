@@ -105,6 +105,10 @@ struct ProfRec {
 };
 static std::mutex g_prof_mu;
 static bool g_prof_on = false;
+static thread_local int g_quiet = 0;  // > 0 inside a CaptureScope
+
+CaptureScope::CaptureScope() { ++g_quiet; }
+CaptureScope::~CaptureScope() { --g_quiet; }
 static std::vector<ProfRec> g_prof;
 static std::vector<hipEvent_t> g_event_pool;
 
@@ -128,7 +132,7 @@ const char* tname()
 
 LaunchScope::LaunchScope(hipStream_t s, double bytes, const char* fmt, ...) : stream_(s), on_(false), idx_(0)
 {
-    if (!g_prof_on) return;
+    if (!g_prof_on || g_quiet > 0) return;
     std::lock_guard<std::mutex> lk(g_prof_mu);
     if (!g_prof_on) return;
     ProfRec r;
@@ -260,7 +264,7 @@ size_t plan_bwd_ws_bytes(const Plan& P, int batch)
 
 // ------------------------------------------------------------- launches
 template <typename T, int M>
-static void launch_fwd_pass_m(const T* in0, const T* in1, T* out0, T* out1, uint64_t in_bs, uint64_t out_bs,
+static void launch_fwd_pass_m(const T* in0, const T* in1, T* out0, T* out1, BMap in_bs, BMap out_bs,
                               uint32_t n_cols, uint32_t log2L, int batch, int ops, hipStream_t s)
 {
     constexpr int NT = 256;
@@ -271,7 +275,7 @@ static void launch_fwd_pass_m(const T* in0, const T* in1, T* out0, T* out1, uint
 }
 
 template <typename T>
-int launch_fwd_pass(int M, const T* in0, const T* in1, T* out0, T* out1, uint64_t in_bs, uint64_t out_bs,
+int launch_fwd_pass(int M, const T* in0, const T* in1, T* out0, T* out1, BMap in_bs, BMap out_bs,
                      uint32_t n_cols, uint32_t log2L, int batch, int ops, hipStream_t s)
 {
     switch (M) {
@@ -285,7 +289,7 @@ int launch_fwd_pass(int M, const T* in0, const T* in1, T* out0, T* out1, uint64_
 }
 
 template <typename T, int M>
-static void launch_fwd_adj_pass_m(const T* in0, const T* in1, T* out0, T* out1, uint64_t in_bs, uint64_t out_bs,
+static void launch_fwd_adj_pass_m(const T* in0, const T* in1, T* out0, T* out1, BMap in_bs, BMap out_bs,
                                   uint32_t n_cols, uint32_t log2L, int batch, hipStream_t s)
 {
     constexpr int NT = 256;
@@ -297,7 +301,7 @@ static void launch_fwd_adj_pass_m(const T* in0, const T* in1, T* out0, T* out1, 
 }
 
 template <typename T>
-int launch_fwd_adj_pass(int M, const T* in0, const T* in1, T* out0, T* out1, uint64_t in_bs, uint64_t out_bs,
+int launch_fwd_adj_pass(int M, const T* in0, const T* in1, T* out0, T* out1, BMap in_bs, BMap out_bs,
                          uint32_t n_cols, uint32_t log2L, int batch, hipStream_t s)
 {
     switch (M) {
@@ -329,7 +333,7 @@ static uint32_t tile_grid(uint64_t n_tiles, int cus, int per_cu)
 }
 
 template <typename T, int K>
-static void launch_fused_k(const T* xt, const T* yt, T* z, uint64_t in_bs, uint64_t z_bs, uint32_t n_tiles,
+static void launch_fused_k(const T* xt, const T* yt, T* z, BMap in_bs, BMap z_bs, uint32_t n_tiles,
                            int batch, int cus, int per_cu, hipStream_t s)
 {
     constexpr int NT = 256;
@@ -340,7 +344,7 @@ static void launch_fused_k(const T* xt, const T* yt, T* z, uint64_t in_bs, uint6
 }
 
 template <typename T>
-int launch_fused(int K, const T* xt, const T* yt, T* z, uint64_t in_bs, uint64_t z_bs, uint32_t n_tiles,
+int launch_fused(int K, const T* xt, const T* yt, T* z, BMap in_bs, BMap z_bs, uint32_t n_tiles,
                   int batch, int cus, int per_cu, hipStream_t s)
 {
     switch (K) {
@@ -365,8 +369,8 @@ int launch_fused(int K, const T* xt, const T* yt, T* z, uint64_t in_bs, uint64_t
 }
 
 template <typename T, int K>
-static void launch_fused_adj_k(const T* xt, const T* yt, const T* w, T* gxt, T* gyt, uint64_t in_bs,
-                               uint64_t w_bs, uint64_t g_bs, uint32_t n_tiles, int batch, int cus, int per_cu,
+static void launch_fused_adj_k(const T* xt, const T* yt, const T* w, T* gxt, T* gyt, BMap in_bs,
+                               BMap w_bs, BMap g_bs, uint32_t n_tiles, int batch, int cus, int per_cu,
                                hipStream_t s)
 {
     constexpr int NT = 256;
@@ -378,8 +382,8 @@ static void launch_fused_adj_k(const T* xt, const T* yt, const T* w, T* gxt, T* 
 }
 
 template <typename T>
-int launch_fused_adj(int K, const T* xt, const T* yt, const T* w, T* gxt, T* gyt, uint64_t in_bs,
-                      uint64_t w_bs, uint64_t g_bs, uint32_t n_tiles, int batch, int cus, int per_cu, hipStream_t s)
+int launch_fused_adj(int K, const T* xt, const T* yt, const T* w, T* gxt, T* gyt, BMap in_bs,
+                      BMap w_bs, BMap g_bs, uint32_t n_tiles, int batch, int cus, int per_cu, hipStream_t s)
 {
     switch (K) {
         case 0: launch_fused_adj_k<T, 0>(xt, yt, w, gxt, gyt, in_bs, w_bs, g_bs, n_tiles, batch, cus, per_cu, s); break;
@@ -397,7 +401,7 @@ int launch_fused_adj(int K, const T* xt, const T* yt, const T* w, T* gxt, T* gyt
 }
 
 template <typename T, int mR, int mW, bool ADJ>
-static void launch_pass_v(const T* src, T* dst, uint64_t src_bs, uint64_t dst_bs, uint64_t L, uint32_t n_hi,
+static void launch_pass_v(const T* src, T* dst, BMap src_bs, BMap dst_bs, uint64_t L, uint32_t n_hi,
                           int batch, int cus, int per_cu, hipStream_t s)
 {
     // register-only passes take 4 waves x 64 columns per workgroup; passes
@@ -418,7 +422,7 @@ static void launch_pass_v(const T* src, T* dst, uint64_t src_bs, uint64_t dst_bs
 }
 
 template <typename T, bool ADJ>
-int launch_pass(const InvPass& ip, const T* src, T* dst, uint64_t src_bs, uint64_t dst_bs, uint64_t L, uint32_t n_hi,
+int launch_pass(const InvPass& ip, const T* src, T* dst, BMap src_bs, BMap dst_bs, uint64_t L, uint32_t n_hi,
                 int batch, int cus, int per_cu, hipStream_t s)
 {
 #define HC_PASS(R, W) \
@@ -435,12 +439,13 @@ int launch_pass(const InvPass& ip, const T* src, T* dst, uint64_t src_bs, uint64
 
 // ------------------------------------------------------------ forward run
 template <typename T>
-int run_forward(const Plan& P, const T* x, const T* y, T* z, int batch, T* ws, int cus, hipStream_t s)
+int run_forward(const Plan& P, const T* x, const T* y, T* z, int batch, T* ws, int cus, hipStream_t s, BMap x_map,
+                BMap z_map)
 {
     const int D = P.D, K = P.K;
     int rc = HC_OK;
     if (P.p == 0) {
-        rc = launch_fused<T>(K, x, y, z, P.n2, P.n3, 1, batch, cus, P.grid_per_cu, s);
+        rc = launch_fused<T>(K, x, y, z, x_map, z_map, 1, batch, cus, P.grid_per_cu, s);
         if (rc != HC_OK) return rc;
     } else {
         T* xt = ws;
@@ -451,7 +456,7 @@ int run_forward(const Plan& P, const T* x, const T* y, T* z, int batch, T* ws, i
         const int n = (int)P.k1.size();
         const T* cx = x;
         const T* cy = y;
-        uint64_t c_bs = P.n2;
+        BMap c_bs = x_map;
         int a = 0;
         for (int i = 0; i < n; ++i) {
             const int M = P.k1[i];
@@ -468,13 +473,13 @@ int run_forward(const Plan& P, const T* x, const T* y, T* z, int batch, T* ws, i
             c_bs = o_bs;
             a += M;
         }
-        rc = launch_fused<T>(K, xt, yt, z, P.xt_elems, P.n3, (uint32_t)pow3u(P.p), batch, cus, P.grid_per_cu, s);
+        rc = launch_fused<T>(K, xt, yt, z, P.xt_elems, z_map, (uint32_t)pow3u(P.p), batch, cus, P.grid_per_cu, s);
         if (rc != HC_OK) return rc;
         for (const InvPass& ip : P.inv) {
             const int m = ip.mR + ip.mW;
             const uint64_t L = pow3u(D - ip.a - m);
             const uint32_t n_hi = (uint32_t)pow3u(ip.a);
-            rc = launch_pass<T, false>(ip, z, z, P.n3, P.n3, L, n_hi, batch, cus, P.grid_per_cu, s);
+            rc = launch_pass<T, false>(ip, z, z, z_map, z_map, L, n_hi, batch, cus, P.grid_per_cu, s);
             if (rc != HC_OK) return rc;
         }
     }
@@ -583,10 +588,12 @@ int run_backward(const Plan& P, const T* x, const T* y, const T* gz, uint64_t gz
     return HC_OK;
 }
 
-template int run_forward<double>(const Plan&, const double*, const double*, double*, int, double*, int, hipStream_t);
-template int run_forward<float>(const Plan&, const float*, const float*, float*, int, float*, int, hipStream_t);
+template int run_forward<double>(const Plan&, const double*, const double*, double*, int, double*, int, hipStream_t,
+                                 BMap, BMap);
+template int run_forward<float>(const Plan&, const float*, const float*, float*, int, float*, int, hipStream_t, BMap,
+                                BMap);
 template int run_forward<uint64_t>(const Plan&, const uint64_t*, const uint64_t*, uint64_t*, int, uint64_t*, int,
-                                   hipStream_t);
+                                   hipStream_t, BMap, BMap);
 template int run_backward<double>(const Plan&, const double*, const double*, const double*, uint64_t, double*,
                                   double*, int, double*, int, hipStream_t);
 template int run_backward<float>(const Plan&, const float*, const float*, const float*, uint64_t, float*, float*,
@@ -665,13 +672,13 @@ int hc_convolve_batch(const void* x, const void* y, void* z, int D, int dtype, i
     switch (dtype) {
         case HC_F64:
             return run_forward<double>(P, (const double*)x, (const double*)y, (double*)z, batch, (double*)workspace,
-                                       cus, stream);
+                                       cus, stream, P.n2, P.n3);
         case HC_F32:
             return run_forward<float>(P, (const float*)x, (const float*)y, (float*)z, batch, (float*)workspace, cus,
-                                      stream);
+                                      stream, P.n2, P.n3);
         default:
             return run_forward<uint64_t>(P, (const uint64_t*)x, (const uint64_t*)y, (uint64_t*)z, batch,
-                                         (uint64_t*)workspace, cus, stream);
+                                         (uint64_t*)workspace, cus, stream, P.n2, P.n3);
     }
 }
 

@@ -1,0 +1,538 @@
+// Batched plans: many pairs of uneven D in one graph launch (see the
+// batched-plan section of include/hc.h for the contract).
+//
+// The pairs are grouped by D.  Each group runs the single-D path (outer
+// forward passes, fused inner tiles, outer inverse passes) once for all of
+// its items: the kernels take per-item offset tables, so every item reads its
+// own x, y slices and writes its own z slice of the packed buffers directly.
+// The groups are independent, so the plan captures them as parallel branches
+// of one HIP graph (fork and join through events), and small groups fill the
+// GPU next to large ones.  Every group's schedule (fused depth, inverse
+// grouping) comes from the default plan or from the autotuner, which times
+// candidates on the group's own shape and requires them to agree bitwise.
+#include "hc.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <type_traits>
+#include <vector>
+
+#include "hc_internal.hpp"
+
+using namespace hc;
+
+namespace {
+
+struct Group {
+    int D = 0;
+    std::vector<int> items;        // pair indices
+    PlanOpts opts;
+    Plan plan;
+    uint64_t ws_off = 0;           // bytes into the plan workspace
+    uint64_t ws_bytes = 0;
+    uint64_t* d_xoff = nullptr;    // per item: element offset into x and y
+    uint64_t* d_zoff = nullptr;    // per item: element offset into z
+    hipStream_t stream = nullptr;  // capture branch
+    hipEvent_t done = nullptr;
+};
+
+// Items per launch are bounded by the grid's y extent.
+constexpr int MAX_ITEMS = 65535;
+
+}  // namespace
+
+struct hc_plan {
+    int dtype = 0;
+    size_t es = 0;
+    unsigned flags = 0;
+    int cus = 0;
+    int n_pairs = 0;
+    std::vector<int> Ds;
+    std::vector<uint64_t> x_off, z_off;  // n_pairs + 1
+    std::vector<Group> groups;
+    uint64_t ws_bytes = 0;
+    double alg_bytes = 0;
+    hipStream_t cap_stream = nullptr;
+    hipEvent_t fork = nullptr;
+    hipGraphExec_t exec = nullptr;
+    const void* g_x = nullptr;
+    const void* g_y = nullptr;
+    void* g_z = nullptr;
+    void* g_ws = nullptr;
+};
+
+namespace hc {
+
+// Algorithmic bytes of one single-D forward for `items` items, counted the
+// way the profiler counts them kernel by kernel.
+static double forward_alg_bytes(const Plan& P, int items)
+{
+    const double es = (double)P.esize;
+    if (P.p == 0) return items * (2.0 * P.n2 + P.n3) * es;
+    double b = 0;
+    int a = 0;
+    for (int M : P.k1) {
+        const double cols = (double)pow3u(a) * (double)(1ull << (P.D - a - M));
+        b += 2.0 * cols * ((1 << M) + pow3c(M)) * es;
+        a += M;
+    }
+    b += (double)pow3u(P.p) * (2.0 * (1 << P.K) + pow3c(P.K)) * es;
+    for (const InvPass& ip : P.inv) {
+        const int m = ip.mR + ip.mW;
+        const double TM = pow3c(m);
+        b += (double)P.n3 / TM * (TM + TM - (1 << m)) * es;
+    }
+    return items * b;
+}
+
+// Group the pairs by D (largest D first, so the big branches start first in
+// the graph) and split groups above MAX_ITEMS.
+static void make_groups(hc_plan* pl)
+{
+    pl->groups.clear();
+    std::vector<std::vector<int>> byD(HC_MAX_D + 1);
+    for (int i = 0; i < pl->n_pairs; ++i) byD[pl->Ds[i]].push_back(i);
+    for (int D = HC_MAX_D; D >= 0; --D) {
+        const std::vector<int>& v = byD[D];
+        for (size_t s = 0; s < v.size(); s += MAX_ITEMS) {
+            Group g;
+            g.D = D;
+            g.items.assign(v.begin() + s, v.begin() + std::min(v.size(), s + MAX_ITEMS));
+            pl->groups.push_back(g);
+        }
+    }
+}
+
+static void free_group_device(Group& g)
+{
+    if (g.d_xoff) (void)hipFree(g.d_xoff);
+    if (g.d_zoff) (void)hipFree(g.d_zoff);
+    if (g.stream) (void)hipStreamDestroy(g.stream);
+    if (g.done) (void)hipEventDestroy(g.done);
+    g.d_xoff = g.d_zoff = nullptr;
+    g.stream = nullptr;
+    g.done = nullptr;
+}
+
+// Fix every group's plan from its options, lay out the workspace and upload
+// the per-item offset tables.
+static int finalize(hc_plan* pl)
+{
+    uint64_t ws = 0;
+    pl->alg_bytes = 0;
+    for (Group& g : pl->groups) {
+        g.plan = make_plan(g.D, pl->dtype, g.opts);
+        const int n = (int)g.items.size();
+        g.ws_off = ws;
+        g.ws_bytes = plan_ws_bytes(g.plan, n);
+        ws += (g.ws_bytes + 255) & ~255ull;
+        pl->alg_bytes += forward_alg_bytes(g.plan, n);
+        std::vector<uint64_t> xo(n), zo(n);
+        for (int b = 0; b < n; ++b) {
+            xo[b] = pl->x_off[g.items[b]];
+            zo[b] = pl->z_off[g.items[b]];
+        }
+        hipError_t e = hipSuccess;
+        if (!g.d_xoff) e = hipMalloc(&g.d_xoff, n * sizeof(uint64_t));
+        if (e == hipSuccess && !g.d_zoff) e = hipMalloc(&g.d_zoff, n * sizeof(uint64_t));
+        if (e == hipSuccess) e = hipMemcpy(g.d_xoff, xo.data(), n * sizeof(uint64_t), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(g.d_zoff, zo.data(), n * sizeof(uint64_t), hipMemcpyHostToDevice);
+        if (e == hipSuccess && !g.stream) e = hipStreamCreateWithFlags(&g.stream, hipStreamNonBlocking);
+        if (e == hipSuccess && !g.done) e = hipEventCreateWithFlags(&g.done, hipEventDisableTiming);
+        if (e != hipSuccess) return hip_fail(e, "batched plan tables");
+    }
+    pl->ws_bytes = ws;
+    return HC_OK;
+}
+
+template <typename T>
+static int enqueue_groups(hc_plan* pl, const void* x, const void* y, void* z, void* ws)
+{
+    hipError_t e = hipEventRecord(pl->fork, pl->cap_stream);
+    if (e != hipSuccess) return hip_fail(e, "fork event");
+    for (Group& g : pl->groups) {
+        if ((e = hipStreamWaitEvent(g.stream, pl->fork, 0)) != hipSuccess) return hip_fail(e, "fork wait");
+        T* gws = ws ? reinterpret_cast<T*>(reinterpret_cast<char*>(ws) + g.ws_off) : nullptr;
+        const int rc = run_forward<T>(g.plan, (const T*)x, (const T*)y, (T*)z, (int)g.items.size(), gws, pl->cus,
+                                      g.stream, BMap(0, g.d_xoff), BMap(0, g.d_zoff));
+        if (rc != HC_OK) return rc;
+        if ((e = hipEventRecord(g.done, g.stream)) != hipSuccess) return hip_fail(e, "join event");
+        if ((e = hipStreamWaitEvent(pl->cap_stream, g.done, 0)) != hipSuccess) return hip_fail(e, "join wait");
+    }
+    return HC_OK;
+}
+
+static int capture(hc_plan* pl, const void* x, const void* y, void* z, void* ws)
+{
+    if (pl->exec) {
+        (void)hipGraphExecDestroy(pl->exec);
+        pl->exec = nullptr;
+    }
+    hipError_t e = hipStreamBeginCapture(pl->cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+    int rc;
+    {
+        CaptureScope quiet;  // the profiler records nothing while capturing
+        switch (pl->dtype) {
+            case HC_F64: rc = enqueue_groups<double>(pl, x, y, z, ws); break;
+            case HC_F32: rc = enqueue_groups<float>(pl, x, y, z, ws); break;
+            default: rc = enqueue_groups<uint64_t>(pl, x, y, z, ws); break;
+        }
+    }
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(pl->cap_stream, &graph);
+    if (rc != HC_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    e = hipGraphInstantiate(&pl->exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+        pl->exec = nullptr;
+        return hip_fail(e, "hipGraphInstantiate");
+    }
+    pl->g_x = x;
+    pl->g_y = y;
+    pl->g_z = z;
+    pl->g_ws = ws;
+    return HC_OK;
+}
+
+// ------------------------------------------------------------ autotuner
+// For every group with outer axes, candidate schedules (fused depth, inverse
+// grouping) are timed on the group's own shape with temporary buffers; all
+// candidates' outputs must agree bit for bit (a disagreement means a race or
+// a bug and fails plan creation).  Results can be kept in a text cache named
+// by HC_TUNE_CACHE (one line per dtype, D and item count).
+__global__ void k_digest(const uint64_t* w, uint64_t n, unsigned long long* out)
+{
+    uint64_t acc = 0;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        acc += w[i] * (2 * i + 1);
+    atomicAdd(out, (unsigned long long)acc);
+}
+
+static std::string cache_key(int dtype, int D, size_t items)
+{
+    return "v1:" + std::to_string(dtype) + ":" + std::to_string(D) + ":" + std::to_string(items);
+}
+
+static bool cache_lookup(const std::string& key, PlanOpts* o)
+{
+    const char* path = getenv("HC_TUNE_CACHE");
+    if (!path) return false;
+    FILE* f = fopen(path, "r");
+    if (!f) return false;
+    char line[512];
+    bool found = false;
+    while (fgets(line, sizeof(line), f)) {
+        char k[256];
+        int K, mm, reg;
+        if (sscanf(line, "%255s %d %d %d", k, &K, &mm, &reg) == 4 && key == k) {
+            o->fused_depth = K;
+            o->inv_group_max = mm;
+            o->inv_reg = reg;
+            found = true;
+        }
+    }
+    fclose(f);
+    return found;
+}
+
+static void cache_store(const std::string& key, const PlanOpts& o)
+{
+    const char* path = getenv("HC_TUNE_CACHE");
+    if (!path) return;
+    FILE* f = fopen(path, "a");
+    if (!f) return;
+    fprintf(f, "%s %d %d %d\n", key.c_str(), o.fused_depth, o.inv_group_max, o.inv_reg);
+    fclose(f);
+}
+
+template <typename T>
+static int tune_group_t(hc_plan* pl, Group& g)
+{
+    const int D = g.D;
+    const int n = (int)g.items.size();
+    std::vector<PlanOpts> cands;
+    const int kmax = max_fused_depth(pl->dtype);
+    for (int K : {kmax, kmax - 1, kmax - 2})
+        for (int reg : {4, 3})
+            for (int mm : {reg + 2, reg + 1, reg}) {
+                PlanOpts o;
+                o.fused_depth = K;
+                o.inv_reg = reg;
+                o.inv_group_max = mm;
+                cands.push_back(o);
+            }
+    uint64_t ws_max = 0;
+    for (const PlanOpts& o : cands) ws_max = std::max<uint64_t>(ws_max, plan_ws_bytes(make_plan(D, pl->dtype, o), n));
+    const uint64_t nx = (uint64_t)n << D, nz = (uint64_t)n * pow3u(D);
+    T *x = nullptr, *y = nullptr, *z = nullptr, *ws = nullptr;
+    unsigned long long* dg = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipMalloc(&x, nx * sizeof(T));
+    if (e == hipSuccess) e = hipMalloc(&y, nx * sizeof(T));
+    if (e == hipSuccess) e = hipMalloc(&z, nz * sizeof(T));
+    if (e == hipSuccess) e = hipMalloc(&ws, std::max<uint64_t>(ws_max, 16));
+    if (e == hipSuccess) e = hipMalloc(&dg, sizeof(unsigned long long));
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    int rc = e == hipSuccess ? HC_OK : hip_fail(e, "autotuner buffers");
+    if (rc == HC_OK) {
+        // inexact inputs in floating point, so the digests compare evaluation orders too
+        std::vector<T> hx(nx);
+        for (uint64_t i = 0; i < nx; ++i) {
+            const int v = (int)((i * 2654435761ull >> 7) % 1000);
+            hx[i] = std::is_integral<T>::value ? (T)(v % 16) : (T)(v / 7.0);
+        }
+        e = hipMemcpy(x, hx.data(), nx * sizeof(T), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(y, hx.data(), nx * sizeof(T), hipMemcpyHostToDevice);
+        if (e != hipSuccess) rc = hip_fail(e, "autotuner inputs");
+    }
+    float best_ms = 1e30f;
+    unsigned long long ref = 0;
+    bool have_ref = false;
+    for (size_t c = 0; rc == HC_OK && c < cands.size(); ++c) {
+        const Plan P = make_plan(D, pl->dtype, cands[c]);
+        auto run = [&]() {
+            return run_forward<T>(P, x, y, z, n, ws, pl->cus, nullptr, BMap(1ull << D), BMap(pow3u(D)));
+        };
+        CaptureScope quiet;  // tuning launches stay out of the profiler's record
+        if ((rc = run()) != HC_OK) break;
+        (void)hipEventRecord(e0, nullptr);
+        for (int r = 0; r < 3 && rc == HC_OK; ++r) rc = run();
+        (void)hipEventRecord(e1, nullptr);
+        if (rc != HC_OK) break;
+        if ((e = hipEventSynchronize(e1)) != hipSuccess) {
+            rc = hip_fail(e, "autotuner sync");
+            break;
+        }
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        unsigned long long digest = 0;
+        e = hipMemset(dg, 0, sizeof(digest));
+        if (e == hipSuccess) {
+            k_digest<<<1024, 256>>>((const uint64_t*)z, nz * sizeof(T) / 8, dg);
+            e = hipMemcpy(&digest, dg, sizeof(digest), hipMemcpyDeviceToHost);
+        }
+        if (e != hipSuccess) {
+            rc = hip_fail(e, "autotuner digest");
+            break;
+        }
+        if (!have_ref) {
+            ref = digest;
+            have_ref = true;
+        } else if (digest != ref) {
+            rc = fail(HC_ERR_HIP, "autotuner: schedule %zu for D=%d produced different bits", c, D);
+            break;
+        }
+        if (ms < best_ms) {
+            best_ms = ms;
+            g.opts = cands[c];
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(x);
+    (void)hipFree(y);
+    (void)hipFree(z);
+    (void)hipFree(ws);
+    (void)hipFree(dg);
+    return rc;
+}
+
+static int tune(hc_plan* pl)
+{
+    for (Group& g : pl->groups) {
+        g.opts = default_opts();
+        if (g.D <= max_fused_depth(pl->dtype)) continue;  // one fused tile: nothing to choose
+        const std::string key = cache_key(pl->dtype, g.D, g.items.size());
+        if (cache_lookup(key, &g.opts)) continue;
+        int rc;
+        switch (pl->dtype) {
+            case HC_F64: rc = tune_group_t<double>(pl, g); break;
+            case HC_F32: rc = tune_group_t<float>(pl, g); break;
+            default: rc = tune_group_t<uint64_t>(pl, g); break;
+        }
+        if (rc != HC_OK) return rc;
+        cache_store(key, g.opts);
+    }
+    return HC_OK;
+}
+
+static void destroy(hc_plan* pl)
+{
+    if (pl->exec) (void)hipGraphExecDestroy(pl->exec);
+    for (Group& g : pl->groups) free_group_device(g);
+    if (pl->fork) (void)hipEventDestroy(pl->fork);
+    if (pl->cap_stream) (void)hipStreamDestroy(pl->cap_stream);
+    delete pl;
+}
+
+static int check_pairs(const int* Ds, int n_pairs, int dtype, unsigned flags)
+{
+    if (!Ds || n_pairs < 1) return fail(HC_ERR_INVALID_ARG, "Ds required, n_pairs >= 1");
+    if ((flags & ~(HC_PLAN_TUNE | HC_PLAN_PERSISTENT)) != 0) return fail(HC_ERR_INVALID_ARG, "unknown plan flag");
+    if (dtype_size(dtype) == 0) return fail(HC_ERR_UNSUPPORTED, "unknown dtype %d", dtype);
+    for (int i = 0; i < n_pairs; ++i)
+        if (Ds[i] < 0 || Ds[i] > 16) return fail(HC_ERR_D_RANGE, "pair %d has D=%d outside [0, 16]", i, Ds[i]);
+    if (flags & HC_PLAN_PERSISTENT)
+        return fail(HC_ERR_UNSUPPORTED, "the single persistent batched kernel is disabled in this library");
+    return HC_OK;
+}
+
+static void layout(hc_plan* pl, const int* Ds, int n_pairs)
+{
+    pl->n_pairs = n_pairs;
+    pl->Ds.assign(Ds, Ds + n_pairs);
+    pl->x_off.assign(n_pairs + 1, 0);
+    pl->z_off.assign(n_pairs + 1, 0);
+    for (int i = 0; i < n_pairs; ++i) {
+        pl->x_off[i + 1] = pl->x_off[i] + (1ull << Ds[i]);
+        pl->z_off[i + 1] = pl->z_off[i] + pow3u(Ds[i]);
+    }
+}
+
+}  // namespace hc
+
+// =================================================================== C ABI
+extern "C" {
+
+int hc_plan_create_batched(const int* Ds, int n_pairs, int dtype, unsigned flags, hc_plan** out)
+{
+    if (!out) return fail(HC_ERR_INVALID_ARG, "out required");
+    *out = nullptr;
+    int rc = check_pairs(Ds, n_pairs, dtype, flags);
+    if (rc != HC_OK) return rc;
+    int cus = 0;
+    if ((rc = device_cus(&cus)) != HC_OK) return rc;
+    hc_plan* pl = new hc_plan();
+    pl->dtype = dtype;
+    pl->es = dtype_size(dtype);
+    pl->flags = flags;
+    pl->cus = cus;
+    layout(pl, Ds, n_pairs);
+    make_groups(pl);
+    hipError_t e = hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&pl->fork, hipEventDisableTiming);
+    rc = e == hipSuccess ? HC_OK : hip_fail(e, "plan stream");
+    if (rc == HC_OK) {
+        if (flags & HC_PLAN_TUNE) rc = tune(pl);
+        else
+            for (Group& g : pl->groups) g.opts = default_opts();
+    }
+    if (rc == HC_OK) rc = finalize(pl);
+    if (rc != HC_OK) {
+        destroy(pl);
+        return rc;
+    }
+    *out = pl;
+    return HC_OK;
+}
+
+int hc_plan_destroy(hc_plan* plan)
+{
+    if (plan) destroy(plan);
+    return HC_OK;
+}
+
+size_t hc_plan_workspace_bytes(const hc_plan* plan) { return plan ? (size_t)plan->ws_bytes : (size_t)-1; }
+
+int hc_plan_layout(const hc_plan* plan, uint64_t* x_offsets, uint64_t* z_offsets)
+{
+    if (!plan) return fail(HC_ERR_INVALID_ARG, "null plan");
+    if (x_offsets) memcpy(x_offsets, plan->x_off.data(), plan->x_off.size() * sizeof(uint64_t));
+    if (z_offsets) memcpy(z_offsets, plan->z_off.data(), plan->z_off.size() * sizeof(uint64_t));
+    return HC_OK;
+}
+
+int hc_plan_execute(hc_plan* plan, const void* x, const void* y, void* z, void* workspace, size_t workspace_bytes,
+                    hipStream_t stream)
+{
+    if (!plan || !x || !y || !z) return fail(HC_ERR_INVALID_ARG, "plan, x, y and z are required");
+    if (misaligned(x) || misaligned(y) || misaligned(z) || misaligned(workspace))
+        return fail(HC_ERR_MISALIGNED, "pointers must be 16-byte aligned");
+    const size_t in_b = plan->x_off.back() * plan->es, out_b = plan->z_off.back() * plan->es;
+    const size_t need = plan->ws_bytes;
+    if (ranges_overlap(z, out_b, x, in_b) || ranges_overlap(z, out_b, y, in_b))
+        return fail(HC_ERR_ALIAS, "z overlaps x or y");
+    if (need > 0) {
+        if (!workspace || workspace_bytes < need) return fail(HC_ERR_WORKSPACE, "workspace of %zu bytes required", need);
+        if (ranges_overlap(workspace, need, z, out_b) || ranges_overlap(workspace, need, x, in_b) ||
+            ranges_overlap(workspace, need, y, in_b))
+            return fail(HC_ERR_ALIAS, "workspace overlaps a data buffer");
+    }
+    if (!plan->exec || plan->g_x != x || plan->g_y != y || plan->g_z != z || plan->g_ws != workspace) {
+        const int rc = capture(plan, x, y, z, workspace);
+        if (rc != HC_OK) return rc;
+    }
+    const char* tn = plan->dtype == HC_F64 ? "f64" : (plan->dtype == HC_F32 ? "f32" : "i64");
+    LaunchScope scope(stream, plan->alg_bytes, "batched_graph<%s>", tn);
+    const hipError_t e = hipGraphLaunch(plan->exec, stream);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    return HC_OK;
+}
+
+int hc_plan_check(hc_plan* plan)
+{
+    if (!plan) return fail(HC_ERR_INVALID_ARG, "null plan");
+    hipError_t e = hipDeviceSynchronize();
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "batched plan execution");
+    return HC_OK;
+}
+
+int hc_plan_describe(const hc_plan* plan, char* buf, size_t len)
+{
+    if (!plan || !buf || len == 0) return fail(HC_ERR_INVALID_ARG, "plan and buffer required");
+    std::string s = "{\"mode\": \"graph\", \"tuned\": " + std::string((plan->flags & HC_PLAN_TUNE) ? "true" : "false") +
+                    ", \"groups\": [";
+    for (size_t i = 0; i < plan->groups.size(); ++i) {
+        const Group& g = plan->groups[i];
+        std::string inv;
+        for (const InvPass& ip : g.plan.inv)
+            inv += (inv.empty() ? "" : ", ") + std::string("\"") + std::to_string(ip.mR) + "+" +
+                   std::to_string(ip.mW) + "\"";
+        s += (i ? ", " : "") + std::string("{\"D\": ") + std::to_string(g.D) +
+             ", \"items\": " + std::to_string(g.items.size()) + ", \"K\": " + std::to_string(g.plan.K) +
+             ", \"inverse_groups\": [" + inv + "]}";
+    }
+    s += "]}";
+    snprintf(buf, len, "%s", s.c_str());
+    return HC_OK;
+}
+
+int hc_plan_inspect(const int* Ds, int n_pairs, int dtype, unsigned flags, int64_t* info, int64_t capacity,
+                    int64_t* n_groups)
+{
+    if (!n_groups || (capacity > 0 && !info)) return fail(HC_ERR_INVALID_ARG, "n_groups (and info) required");
+    const int rc = check_pairs(Ds, n_pairs, dtype, flags & ~HC_PLAN_TUNE);
+    if (rc != HC_OK) return rc;
+    hc_plan pl;
+    pl.dtype = dtype;
+    pl.es = dtype_size(dtype);
+    layout(&pl, Ds, n_pairs);
+    make_groups(&pl);
+    *n_groups = (int64_t)pl.groups.size();
+    for (size_t i = 0; i < pl.groups.size() && (int64_t)i < capacity; ++i) {
+        const Group& g = pl.groups[i];
+        const Plan P = make_plan(g.D, dtype, default_opts());
+        int64_t* r = info + 6 * i;
+        r[0] = g.D;
+        r[1] = (int64_t)g.items.size();
+        r[2] = g.items.front();
+        r[3] = P.K;
+        r[4] = (int64_t)P.k1.size();
+        r[5] = (int64_t)P.inv.size();
+    }
+    return HC_OK;
+}
+
+}  // extern "C"

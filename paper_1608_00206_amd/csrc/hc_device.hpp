@@ -173,6 +173,16 @@ __device__ __forceinline__ void fwd_adj_group(T (&s)[pow3c(M)])
     fwd_adj_steps<T, M, M - 1>(s);
 }
 
+// --------------------------------------------------------- batch items
+// Element offset of batch item b in one buffer: a uniform stride, or a
+// per-item table (device memory) when the items are packed unevenly.
+struct BMap {
+    uint64_t stride = 0;
+    const uint64_t* table = nullptr;
+    __host__ __device__ BMap(uint64_t s = 0, const uint64_t* t = nullptr) : stride(s), table(t) {}
+    __device__ __forceinline__ uint64_t at(uint32_t b) const { return table ? table[b] : (uint64_t)b * stride; }
+};
+
 // -------------------------------------------------------- tile scheduling
 // Map a workgroup to its first tile so that each XCD (workgroups are handed
 // to the 8 XCDs round-robin) walks one contiguous chunk of tiles: neighbouring

@@ -7,6 +7,8 @@
 
 #include <vector>
 
+#include "hc_device.hpp"
+
 namespace hc {
 
 // One outer inverse pass over the axes [a, a + mR + mW): mR axes held in
@@ -52,6 +54,16 @@ class LaunchScope {
     size_t idx_;
 };
 
+// While alive, LaunchScope records nothing on this thread (used while a
+// graph is captured and while the autotuner times candidates).
+class CaptureScope {
+  public:
+    CaptureScope();
+    ~CaptureScope();
+    CaptureScope(const CaptureScope&) = delete;
+    CaptureScope& operator=(const CaptureScope&) = delete;
+};
+
 int fail(int code, const char* fmt, ...);
 int hip_fail(hipError_t e, const char* what);
 uint64_t pow3u(int n);
@@ -65,8 +77,11 @@ PlanOpts default_opts(bool backward = false);
 size_t plan_ws_bytes(const Plan& P, int batch);
 size_t plan_bwd_ws_bytes(const Plan& P, int batch);
 
+// Forward path for `batch` items of one D; x_map / z_map give each item's
+// element offset in x, y and z (uniform strides or per-item tables).
 template <typename T>
-int run_forward(const Plan& P, const T* x, const T* y, T* z, int batch, T* ws, int cus, hipStream_t s);
+int run_forward(const Plan& P, const T* x, const T* y, T* z, int batch, T* ws, int cus, hipStream_t s, BMap x_map,
+                BMap z_map);
 template <typename T>
 int run_backward(const Plan& P, const T* x, const T* y, const T* gz, uint64_t gz_bs, T* gx, T* gy, int batch,
                  T* ws, int cus, hipStream_t s);

@@ -51,14 +51,13 @@ __device__ __forceinline__ void fwd_column(const T* __restrict__ in, T* __restri
 template <typename T, int M, int NT>
 __global__ __launch_bounds__(NT) void k_fwd_pass(const T* __restrict__ in0, const T* __restrict__ in1,
                                                  T* __restrict__ out0, T* __restrict__ out1,
-                                                 uint64_t in_bstride, uint64_t out_bstride,
-                                                 uint32_t n_cols, uint32_t log2L)
+                                                 BMap in_map, BMap out_map, uint32_t n_cols, uint32_t log2L)
 {
     const T* in = blockIdx.z ? in1 : in0;
     T* out = blockIdx.z ? out1 : out0;
     const uint32_t c = blockIdx.x * NT + threadIdx.x;
     if (c >= n_cols) return;
-    fwd_column<T, M>(in + (uint64_t)blockIdx.y * in_bstride, out + (uint64_t)blockIdx.y * out_bstride, c, log2L);
+    fwd_column<T, M>(in + in_map.at(blockIdx.y), out + out_map.at(blockIdx.y), c, log2L);
 }
 
 // =========================================================================
@@ -211,14 +210,14 @@ __device__ __forceinline__ void fused_tile(const T* __restrict__ xr, const T* __
 
 template <typename T, int K, int NT>
 __global__ __launch_bounds__(NT) void k_fused_inner(const T* __restrict__ xt, const T* __restrict__ yt,
-                                                    T* __restrict__ z, uint64_t in_bstride,
-                                                    uint64_t z_bstride, uint32_t n_tiles)
+                                                    T* __restrict__ z, BMap in_map, BMap z_map,
+                                                    uint32_t n_tiles)
 {
     using C = FusedCfg<K>;
     __shared__ T lds[C::LDS];
-    xt += (uint64_t)blockIdx.y * in_bstride;
-    yt += (uint64_t)blockIdx.y * in_bstride;
-    z += (uint64_t)blockIdx.y * z_bstride;
+    xt += in_map.at(blockIdx.y);
+    yt += in_map.at(blockIdx.y);
+    z += z_map.at(blockIdx.y);
     const TileWalk w = xcd_tile_walk(n_tiles);
     for (uint32_t o = w.first; o < w.end; o += w.step) {
         lds_barrier();  // the previous tile's P5 reads of Z are done
@@ -357,14 +356,14 @@ __device__ __forceinline__ void inv_tile(const T* src, T* dst, uint64_t L, uint3
 }
 
 template <typename T, int mR, int mW, int CW, bool ADJ>
-__global__ __launch_bounds__(64 * pow3c(mW) * CW) void k_inv_pass(const T* src, T* dst, uint64_t src_bstride,
-                                                                 uint64_t dst_bstride, uint64_t L,
-                                                                 uint32_t tiles_per_hi, uint32_t n_tiles)
+__global__ __launch_bounds__(64 * pow3c(mW) * CW) void k_inv_pass(const T* src, T* dst, BMap src_map,
+                                                                 BMap dst_map, uint64_t L, uint32_t tiles_per_hi,
+                                                                 uint32_t n_tiles)
 {
     using P = PassCfg<mR, mW, CW>;
     __shared__ T S[P::LDS > 0 ? P::LDS : 1];
-    src += (uint64_t)blockIdx.y * src_bstride;
-    dst += (uint64_t)blockIdx.y * dst_bstride;
+    src += src_map.at(blockIdx.y);
+    dst += dst_map.at(blockIdx.y);
     const bool in_place = (src == dst);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const TileWalk walk = xcd_tile_walk(n_tiles);
@@ -401,16 +400,14 @@ __device__ __forceinline__ void fwd_adj_column(const T* __restrict__ in, T* __re
 template <typename T, int M, int NT>
 __global__ __launch_bounds__(NT) void k_fwd_adj_pass(const T* __restrict__ in0, const T* __restrict__ in1,
                                                      T* __restrict__ out0, T* __restrict__ out1,
-                                                     uint64_t in_bstride, uint64_t out_bstride,
-                                                     uint32_t n_cols, uint32_t log2L)
+                                                     BMap in_map, BMap out_map, uint32_t n_cols, uint32_t log2L)
 {
     const T* in = blockIdx.z ? in1 : in0;
     T* out = blockIdx.z ? out1 : out0;
     if (out == nullptr) return;
     const uint32_t c = blockIdx.x * NT + threadIdx.x;
     if (c >= n_cols) return;
-    fwd_adj_column<T, M>(in + (uint64_t)blockIdx.y * in_bstride, out + (uint64_t)blockIdx.y * out_bstride, c,
-                         log2L);
+    fwd_adj_column<T, M>(in + in_map.at(blockIdx.y), out + out_map.at(blockIdx.y), c, log2L);
 }
 
 // =========================================================================
@@ -545,17 +542,16 @@ __device__ __forceinline__ void fused_tile_adj(const T* __restrict__ xr, const T
 template <typename T, int K, int NT>
 __global__ __launch_bounds__(NT) void k_fused_inner_adj(const T* __restrict__ xt, const T* __restrict__ yt,
                                                         const T* __restrict__ w, T* __restrict__ gxt,
-                                                        T* __restrict__ gyt, uint64_t in_bstride,
-                                                        uint64_t w_bstride, uint64_t g_bstride,
-                                                        uint32_t n_tiles)
+                                                        T* __restrict__ gyt, BMap in_map, BMap w_map,
+                                                        BMap g_map, uint32_t n_tiles)
 {
     using C = FusedCfg<K>;
     __shared__ T lds[C::ADJ_LDS];
-    xt += (uint64_t)blockIdx.y * in_bstride;
-    yt += (uint64_t)blockIdx.y * in_bstride;
-    w += (uint64_t)blockIdx.y * w_bstride;
-    if (gxt) gxt += (uint64_t)blockIdx.y * g_bstride;
-    if (gyt) gyt += (uint64_t)blockIdx.y * g_bstride;
+    xt += in_map.at(blockIdx.y);
+    yt += in_map.at(blockIdx.y);
+    w += w_map.at(blockIdx.y);
+    if (gxt) gxt += g_map.at(blockIdx.y);
+    if (gyt) gyt += g_map.at(blockIdx.y);
     const TileWalk walk = xcd_tile_walk(n_tiles);
     for (uint32_t o = walk.first; o < walk.end; o += walk.step) {
         lds_barrier();

@@ -127,3 +127,21 @@ def test_product_package_does_not_import_oracle():
             if f.endswith((".py", ".hip", ".hpp", ".h", ".cpp")):
                 text = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in text and "hc_oracle" not in text and "liboracle" not in text, f
+
+
+def test_plan_validation():
+    f = _abi.lib().hc_plan_create_batched
+    import ctypes
+    Ds = (ctypes.c_int * 3)(4, 9, 12)
+    out = ctypes.c_void_p(0)
+    assert f(None, 3, 0, 0, ctypes.byref(out)) == 1
+    assert f(Ds, 0, 0, 0, ctypes.byref(out)) == 1
+    assert f(Ds, 3, 0, 0, None) == 1
+    assert f(Ds, 3, 0, 8, ctypes.byref(out)) == 1          # unknown flag
+    assert f(Ds, 3, 0, 2, ctypes.byref(out)) == 3          # persistent kernel disabled
+    assert f(Ds, 3, 7, 0, ctypes.byref(out)) == 3          # unknown dtype
+    bad = (ctypes.c_int * 2)(4, 17)
+    assert f(bad, 2, 0, 0, ctypes.byref(out)) == 2
+    assert _abi.lib().hc_plan_workspace_bytes(None) == _abi.SIZE_MAX
+    assert _abi.lib().hc_plan_destroy(None) == 0
+    assert _abi.lib().hc_plan_execute(None, 0, 0, 0, 0, 0, None) == 1
