@@ -35,7 +35,8 @@
  *     hot path allocates; plans allocate their own small tables when created.
  *   - Inputs are read-only (unlike the paper's listing, which overwrites x
  *     and y).  Outputs must not overlap inputs or the workspace.
- *   - All data and workspace pointers must be 16-byte aligned.
+ *   - Data pointers must be aligned to their element size (8 bytes for
+ *     HC_F64/HC_I64, 4 for HC_F32); workspaces to 16 bytes.
  *   - Work is enqueued on `stream` (0 = the null stream); nothing synchronises.
  *   - Argument errors are detected on the host before anything is enqueued.
  *     Faults inside kernels surface asynchronously, as HC_ERR_HIP from a
@@ -71,7 +72,7 @@ typedef enum hc_status {
     HC_ERR_D_RANGE = 2,     /* D < 0 or D > HC_MAX_D */
     HC_ERR_UNSUPPORTED = 3, /* dtype not supported by this entry point */
     HC_ERR_ALIAS = 4,       /* an output overlaps an input or the workspace */
-    HC_ERR_MISALIGNED = 5,  /* a pointer is not 16-byte aligned */
+    HC_ERR_MISALIGNED = 5,  /* a pointer is not aligned to its element size */
     HC_ERR_WORKSPACE = 6,   /* workspace missing or smaller than required */
     HC_ERR_NO_DEVICE = 7,   /* no usable HIP device */
     HC_ERR_HIP = 8          /* a HIP runtime call failed */
@@ -203,8 +204,8 @@ int hc_plan_layout(const hc_plan* plan, uint64_t* x_offsets, uint64_t* z_offsets
 
 /*
  * Run the plan: z = x * y for every pair of the packed buffers.  x, y, z and
- * the workspace follow the conventions above (device, 16-byte aligned, z
- * disjoint from the others).  Enqueued on `stream` as one graph launch.
+ * the workspace follow the conventions above (device, aligned, z disjoint
+ * from the others).  Enqueued on `stream` as one graph launch.
  * Errors: HC_ERR_INVALID_ARG, HC_ERR_ALIAS, HC_ERR_MISALIGNED,
  * HC_ERR_WORKSPACE, HC_ERR_HIP.
  */

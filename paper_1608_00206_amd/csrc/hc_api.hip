@@ -62,9 +62,9 @@ bool ranges_overlap(const void* a, size_t na, const void* b, size_t nb)
     return a0 < b0 + nb && b0 < a0 + na;
 }
 
-bool misaligned(const void* p)
+bool misaligned(const void* p, size_t align)
 {
-    return p && ((uintptr_t)p & 15u) != 0;
+    return p && ((uintptr_t)p & (align - 1)) != 0;
 }
 
 // ------------------------------------------------------------------ device
@@ -651,8 +651,8 @@ int hc_convolve_batch(const void* x, const void* y, void* z, int D, int dtype, i
     const size_t es = dtype_size(dtype);
     if (es == 0) return fail(HC_ERR_UNSUPPORTED, "unknown dtype %d", dtype);
     if (batch < 1 || batch > 65535) return fail(HC_ERR_INVALID_ARG, "batch=%d outside [1, 65535]", batch);
-    if (misaligned(x) || misaligned(y) || misaligned(z) || misaligned(workspace))
-        return fail(HC_ERR_MISALIGNED, "pointers must be 16-byte aligned");
+    if (misaligned(x, es) || misaligned(y, es) || misaligned(z, es) || misaligned(workspace, 16))
+        return fail(HC_ERR_MISALIGNED, "data must be aligned to the element size, the workspace to 16 bytes");
     const Plan P = make_plan(D, dtype, default_opts());
     const size_t in_b = (size_t)batch * P.n2 * es, out_b = (size_t)batch * P.n3 * es;
     const size_t need = plan_ws_bytes(P, batch);
@@ -703,9 +703,9 @@ int hc_convolve_backward_batch(const void* x, const void* y, const void* grad_z,
     const Plan P = make_plan(D, dtype, default_opts(true));
     if (grad_z_stride != 0 && (grad_z_stride < 0 || (uint64_t)grad_z_stride < P.n3))
         return fail(HC_ERR_INVALID_ARG, "grad_z_stride must be 0 or at least 3^D");
-    if (misaligned(x) || misaligned(y) || misaligned(grad_z) || misaligned(grad_x) || misaligned(grad_y) ||
-        misaligned(workspace))
-        return fail(HC_ERR_MISALIGNED, "pointers must be 16-byte aligned");
+    if (misaligned(x, es) || misaligned(y, es) || misaligned(grad_z, es) || misaligned(grad_x, es) ||
+        misaligned(grad_y, es) || misaligned(workspace, 16))
+        return fail(HC_ERR_MISALIGNED, "data must be aligned to the element size, the workspace to 16 bytes");
     const size_t in_b = (size_t)batch * P.n2 * es;
     const size_t gz_b = (grad_z_stride == 0 ? P.n3 : (size_t)grad_z_stride * (batch - 1) + P.n3) * es;
     const size_t need = plan_bwd_ws_bytes(P, batch);

@@ -457,8 +457,8 @@ int hc_plan_execute(hc_plan* plan, const void* x, const void* y, void* z, void* 
                     hipStream_t stream)
 {
     if (!plan || !x || !y || !z) return fail(HC_ERR_INVALID_ARG, "plan, x, y and z are required");
-    if (misaligned(x) || misaligned(y) || misaligned(z) || misaligned(workspace))
-        return fail(HC_ERR_MISALIGNED, "pointers must be 16-byte aligned");
+    if (misaligned(x, plan->es) || misaligned(y, plan->es) || misaligned(z, plan->es) || misaligned(workspace, 16))
+        return fail(HC_ERR_MISALIGNED, "data must be aligned to the element size, the workspace to 16 bytes");
     const size_t in_b = plan->x_off.back() * plan->es, out_b = plan->z_off.back() * plan->es;
     const size_t need = plan->ws_bytes;
     if (ranges_overlap(z, out_b, x, in_b) || ranges_overlap(z, out_b, y, in_b))

@@ -69,7 +69,7 @@ int hip_fail(hipError_t e, const char* what);
 uint64_t pow3u(int n);
 size_t dtype_size(int dtype);
 bool ranges_overlap(const void* a, size_t na, const void* b, size_t nb);
-bool misaligned(const void* p);
+bool misaligned(const void* p, size_t align);
 int device_cus(int* cus);
 int max_fused_depth(int dtype);
 Plan make_plan(int D, int dtype, const PlanOpts& o);

@@ -69,7 +69,8 @@ def _conv(x=FAKE, y=FAKE + (1 << 20), z=FAKE + (1 << 24), D=10, dtype=0, ws=0, w
     (dict(D=-1), 2), (dict(D=22), 2),
     (dict(dtype=3), 3), (dict(dtype=-1), 3),
     (dict(batch=0), 1), (dict(batch=70000), 1),
-    (dict(x=FAKE + 8), 5), (dict(z=FAKE + (1 << 24) + 4), 5),
+    (dict(x=FAKE + 4), 5), (dict(z=FAKE + (1 << 24) + 4), 5), (dict(dtype=1, y=FAKE + (1 << 20) + 2), 5),
+    (dict(D=12, ws=FAKE + (1 << 30) + 8, wsb=1 << 30), 5),
     (dict(z=FAKE + 64), 4),                      # z overlaps x
     (dict(D=12), 6),                              # workspace required but missing
     (dict(D=12, ws=FAKE + (1 << 30), wsb=16), 6),  # too small

@@ -155,3 +155,17 @@ def test_errors_raise():
     with pytest.raises(hc.HCError) as e:
         hc._abi.check(hc._abi.hc_convolve(x.data_ptr(), x.data_ptr(), x.data_ptr() + 16, 3, 0, 0, 0, 0))
     assert e.value.status == "HC_ERR_ALIAS"
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_element_aligned_slices(dtype):
+    """Inputs and output at odd element offsets (as inside packed batches)."""
+    D = 11
+    x, y = _pair(D, dtype, seed=9)
+    X = on_gpu(np.concatenate([np.zeros(1, dtype), x]))
+    Y = on_gpu(np.concatenate([np.zeros(3, dtype), y]))
+    Z = torch.zeros(3 ** D + 5, dtype=TORCH[np.dtype(dtype)], device=DEV)
+    hc.convolve(X[1:], Y[3:], out=Z[5:])
+    torch.cuda.synchronize(DEV)
+    check(Z[5:].cpu().numpy(), oracle.canonical(x, y), "odd offsets")
+    assert not Z[:5].any().item()
