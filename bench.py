@@ -26,6 +26,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -67,6 +68,82 @@ def measured_traffic(kernel: str, launches_per_step: float):
     if not k:
         return None
     return (k["fetch_kib"] * t["fetch_scale"] + k["write_kib"] * t["write_scale"]) * 1024.0
+
+
+COPY_CAL_BYTES = 1 << 31  # read once and written once by the calibration copy
+
+
+def copy_calibration(torch) -> None:
+    """One plain copy kernel over a known number of bytes (torch's elementwise
+    negation: every element read once, written once), run before the
+    workload so that a rocprofv3 counter pass sees it beside the kernels."""
+    n = COPY_CAL_BYTES // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    torch.neg(src, out=dst)
+    torch.cuda.synchronize()
+    del src, dst
+    torch.cuda.empty_cache()
+    log(f"copy calibration: {COPY_CAL_BYTES} bytes read, {COPY_CAL_BYTES} bytes written")
+
+
+_DT = {"double": "f64", "float": "f32", "long": "i64", "long long": "i64"}
+
+
+def profiler_name(demangled: str):
+    """The library profiler's name for a kernel from its demangled symbol."""
+    m = re.match(r"(?:void )?hc::k_(\w+)<([^,>]+)((?:, *[^,>]+)*)>", demangled)
+    if not m:
+        return None
+    base, dt = m.group(1), _DT.get(m.group(2).strip())
+    args = [a.strip() for a in m.group(3).split(",") if a.strip()]
+    if dt is None:
+        return None
+    if base == "inv_pass":
+        kind = "inv_adj_pass" if args[3] == "true" else "inv_pass"
+        return f"{kind}<{dt},{args[0]}+{args[1]}>"
+    if base in ("fused_inner", "fused_inner_adj"):
+        return f"{base}<{dt},K={args[0]}>"
+    if base in ("fwd_pass", "fwd_adj_pass"):
+        return f"{base}<{dt},M={args[0]}>"
+    return None
+
+
+def write_traffic(fetch_csv: str, write_csv: str) -> None:
+    """Turns two rocprofv3 counter passes (FETCH_SIZE, then WRITE_SIZE, both
+    over `--workload ... --copy-calibration`) into the traffic table: KiB per
+    dispatch averaged per kernel, and the factors that map each counter onto
+    the calibration copy's known bytes."""
+    import csv
+
+    def per_kernel(path, counter):
+        acc, cal = {}, []
+        with open(path, newline="") as f:
+            for row in csv.DictReader(f):
+                if row.get("Counter_Name") != counter:
+                    continue
+                name, val = row["Kernel_Name"], float(row["Counter_Value"])
+                if "neg" in name and "hc::" not in name:
+                    cal.append(val)
+                    continue
+                pn = profiler_name(name)
+                if pn is not None:
+                    acc.setdefault(pn, []).append(val)
+        if len(cal) != 1:
+            raise SystemExit(f"{path}: expected one calibration copy dispatch, found {len(cal)}")
+        return {k: sum(v) / len(v) for k, v in acc.items()}, cal[0]
+
+    fetch, fcal = per_kernel(fetch_csv, "FETCH_SIZE")
+    write, wcal = per_kernel(write_csv, "WRITE_SIZE")
+    out = {"kernel_source_sha": kernel_source_hash(), "unit": "KiB per dispatch",
+           "copy_calibration_bytes": COPY_CAL_BYTES, "copy_fetch_kib": fcal, "copy_write_kib": wcal,
+           "fetch_scale": COPY_CAL_BYTES / (fcal * 1024.0), "write_scale": COPY_CAL_BYTES / (wcal * 1024.0),
+           "kernels": {k: {"fetch_kib": fetch[k], "write_kib": write[k]} for k in sorted(fetch) if k in write}}
+    with open(TRAFFIC_FILE, "w") as f:
+        json.dump(out, f, indent=1)
+        f.write("\n")
+    print(json.dumps(out, indent=1))
 
 
 def time_steps(fn, steps: int, warmup: int, torch):
@@ -304,7 +381,14 @@ def main():
     ap.add_argument("--workload", default="all",
                     choices=["all", "d20", "d16-f64", "d16-i64", "d10", "batched", "backward"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run one plain copy kernel of known size before the workload (for counter passes)")
+    ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write profiles/traffic.json from two rocprofv3 counter CSVs and exit")
     args = ap.parse_args()
+    if args.write_traffic:
+        write_traffic(*args.write_traffic)
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py: this build runs on one GPU only; --gpus must be 1 "
@@ -317,6 +401,8 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py: no GPU visible", file=sys.stderr)
         sys.exit(1)
+    if args.copy_calibration:
+        copy_calibration(torch)
     if args.workload == "backward":
         res = run_backward(args, torch, hc)
     elif args.workload == "batched":
