@@ -410,15 +410,22 @@ static void launch_pass_v(const T* src, T* dst, BMap src_bs, BMap dst_bs, uint64
     using PC = PassCfg<mR, mW, CW>;
     const uint32_t tiles_per_hi = (uint32_t)((L + PC::COLS - 1) / PC::COLS);
     const uint64_t n_tiles = (uint64_t)tiles_per_hi * n_hi;
-    dim3 grid(tile_grid(n_tiles, cus, per_cu), batch, 1);
+    // the streamed-thirds tile runs one tile per workgroup
+    dim3 grid(tile_grid(n_tiles, cus, PC::THIRDS ? 0 : per_cu), batch, 1);
     // reads every entry; writes the entries the map changes (all if out of place)
     constexpr int TM = pow3c(mR + mW);
     const double n_cols = (double)batch * n_hi * L;
     const double writes = src != dst ? TM : (ADJ ? TM - 1 : TM - (1 << (mR + mW)));
     const double bytes = n_cols * (TM + writes) * sizeof(T);
     LaunchScope scope(s, bytes, "%s<%s,%d+%d>", ADJ ? "inv_adj_pass" : "inv_pass", tname<T>(), mR, mW);
-    k_inv_pass<T, mR, mW, CW, ADJ><<<grid, PC::NT, 0, s>>>(src, dst, src_bs, dst_bs, L, tiles_per_hi,
-                                                           (uint32_t)n_tiles);
+    // in place (the same buffer and the same per-item offsets): entries the
+    // map leaves unchanged are not written back
+    if (src == dst && src_bs.stride == dst_bs.stride && src_bs.table == dst_bs.table)
+        k_inv_pass<T, mR, mW, CW, ADJ, true><<<grid, PC::NT, 0, s>>>(src, dst, src_bs, dst_bs, L, tiles_per_hi,
+                                                                     (uint32_t)n_tiles);
+    else
+        k_inv_pass<T, mR, mW, CW, ADJ, false><<<grid, PC::NT, 0, s>>>(src, dst, src_bs, dst_bs, L, tiles_per_hi,
+                                                                      (uint32_t)n_tiles);
 }
 
 template <typename T, bool ADJ>

@@ -173,6 +173,46 @@ __device__ __forceinline__ void fwd_adj_group(T (&s)[pow3c(M)])
     fwd_adj_steps<T, M, M - 1>(s);
 }
 
+// ------------------------------------------------------- buffer accesses
+// A row segment addressed through a buffer resource: the wave-uniform base
+// address and byte bound live in scalar registers, each lane supplies a
+// 32-bit byte offset.  This keeps per-row addressing out of the vector
+// register file, and the hardware bound check turns accesses at or past
+// `bytes` into loads of zero and dropped stores (the ragged column tail).
+// Word 3 = 0x00020000: raw (untyped) 32-bit data access on gfx9-family parts.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const void* base, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+
+template <typename T>
+__device__ __forceinline__ T buf_load(__amdgpu_buffer_rsrc_t r, uint32_t off)
+{
+    static_assert(sizeof(T) == 8 || sizeof(T) == 4, "8- or 4-byte elements");
+    if constexpr (sizeof(T) == 8) return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+    else return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+
+template <typename T>
+__device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, uint32_t off, T v)
+{
+    if constexpr (sizeof(T) == 8) {
+        using V2 = unsigned int __attribute__((ext_vector_type(2)));
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V2, v), r, off, 0, 0);
+    } else {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, off, 0, 0);
+    }
+}
+
+// A per-lane value the compiler must take as given at this point: it keeps
+// one register for it and folds constant offsets into the instructions that
+// use it, instead of materialising one address per access.
+__device__ __forceinline__ uint32_t opaque_u32(uint32_t x)
+{
+    asm volatile("" : "+v"(x));
+    return x;
+}
+
 // --------------------------------------------------------- batch items
 // Element offset of batch item b in one buffer: a uniform stride, or a
 // per-item table (device memory) when the items are packed unevenly.

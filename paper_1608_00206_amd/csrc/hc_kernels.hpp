@@ -246,10 +246,9 @@ __global__ __launch_bounds__(NT) void k_fused_inner(const T* __restrict__ xt, co
 // Entries the map leaves unchanged are not stored when src == dst:
 //   G   changes entries with a 1 among the group digits,
 //   G^T changes entries whose group digits are not all 1.
-// Columns past L: a wave whose 64 columns all lie past L does nothing; other
-// lanes past L re-read and re-write their wave's first column with the value
-// that column's own lane computes (identical stores in the same instruction,
-// every access in bounds).
+// Rows are addressed through buffer resources (row_rsrc) whose byte bound
+// ends at column L: lanes past L load zeros and their stores are dropped, and
+// a wave whose 64 columns all lie past L does nothing.
 // =========================================================================
 template <int mR, int mW, int CW>
 struct PassCfg {
@@ -261,16 +260,18 @@ struct PassCfg {
     static constexpr int S_GA = tR < 9 ? tR : 9;          // register indices per sub-round
     static constexpr int NSUB = (tR + S_GA - 1) / S_GA;
     static constexpr int Q = (S_GA + tW - 1) / tW;        // register indices per wave per sub-round
-    static constexpr int LDS = mW == 0 ? 0 : 2 * tW * S_GA * 64;  // elements
+    // mR = 4 with a wave part streams thirds (inv_tile_r4): three sub-round
+    // buffers hold one third of the register indices at once
+    static constexpr bool THIRDS = mR == 4 && mW > 0;
+    static constexpr int LDS = mW == 0 ? 0 : (THIRDS ? 3 : 2) * tW * S_GA * 64;  // elements
 };
 
 // One tile of an inverse pass.  `wave` must be wave-uniform; waves with
 // wave >= PassCfg::WAVES take part in the barriers only.  S holds
 // PassCfg::LDS elements when mW > 0.  EXACT: the workgroup has exactly
 // PassCfg::WAVES waves and, when mW > 0, every wave is known to be active.
-template <typename T, int mR, int mW, int CW, bool ADJ, bool EXACT = false>
-__device__ __forceinline__ void inv_tile(const T* src, T* dst, uint64_t L, uint32_t hi, uint32_t j, bool in_place,
-                                         int wave, T* S)
+template <typename T, int mR, int mW, int CW, bool ADJ, bool IN_PLACE, bool EXACT = false>
+__device__ __forceinline__ void inv_tile(const T* src, T* dst, uint64_t L, uint32_t hi, uint32_t j, int wave, T* S)
 {
     using P = PassCfg<mR, mW, CW>;
     constexpr int tR = P::tR, tW = P::tW, TM = tR * tW;
@@ -281,8 +282,8 @@ __device__ __forceinline__ void inv_tile(const T* src, T* dst, uint64_t L, uint3
     const uint64_t lo_w = (uint64_t)j * P::COLS + (uint64_t)cg * 64;  // this wave's first column
     // with a wave part the tile's first column lo_w = j * 64 is always < L
     const bool active = (EXACT && mW > 0) ? true : (wave < P::WAVES && lo_w < L);
-    const uint32_t col = (lo_w + lane < L) ? lane : 0;
-    const uint32_t col_off = col * (uint32_t)sizeof(T);
+    const uint32_t col_off = (uint32_t)lane * (uint32_t)sizeof(T);
+    const uint32_t seg_bytes = (uint32_t)((L - lo_w < 64 ? L - lo_w : 64) * sizeof(T));  // when active
     const uint64_t row_bytes = L * sizeof(T);
     const uint64_t tile_off = ((uint64_t)hi * TM * L + lo_w) * sizeof(T);
     const char* s_tile = reinterpret_cast<const char*>(src) + tile_off;
@@ -294,7 +295,7 @@ __device__ __forceinline__ void inv_tile(const T* src, T* dst, uint64_t L, uint3
         const char* rp = s_tile + (uint64_t)(ADJ ? gW1 : gW1 * tInner) * row_bytes;
 #pragma unroll
         for (int gR = 0; gR < tR; ++gR) {
-            v[gR] = *reinterpret_cast<const T*>(rp + col_off);
+            v[gR] = buf_load<T>(row_rsrc(rp, seg_bytes), col_off);
             rp += step;
         }
         if constexpr (ADJ) inv_adj_group<T, mR>(v);
@@ -304,7 +305,7 @@ __device__ __forceinline__ void inv_tile(const T* src, T* dst, uint64_t L, uint3
 #pragma unroll
             for (int gR = 0; gR < tR; ++gR) {
                 const bool changed = ADJ ? !all_digits_one(gR, mR) : has_digit_one(gR, mR);
-                if (changed || !in_place) *reinterpret_cast<T*>(wp + col_off) = v[gR];
+                if (changed || !IN_PLACE) buf_store<T>(row_rsrc(wp, seg_bytes), col_off, v[gR]);
                 wp += row_bytes;
             }
         }
@@ -346,7 +347,7 @@ __device__ __forceinline__ void inv_tile(const T* src, T* dst, uint64_t L, uint3
                     for (int gW = 0; gW < tW; ++gW) {
                         const bool changed = ADJ ? !(r_flag && all_digits_one(gW, mW))
                                                  : (r_flag || has_digit_one(gW, mW));
-                        if (changed || !in_place) *reinterpret_cast<T*>(wp + col_off) = u[gW];
+                        if (changed || !IN_PLACE) buf_store<T>(row_rsrc(wp, seg_bytes), col_off, u[gW]);
                         wp += step;
                     }
                 }
@@ -355,7 +356,163 @@ __device__ __forceinline__ void inv_tile(const T* src, T* dst, uint64_t L, uint3
     }
 }
 
-template <typename T, int mR, int mW, int CW, bool ADJ>
+// One tile of an inverse pass with mR = 4 and a wave part (CW = 1, every wave
+// active).  The 81 register values of a lane would not fit the register budget
+// of a 3^mW-wave workgroup, so the register sub-cube is streamed in thirds of
+// its outermost register axis d0 (register index gR = d0*27 + rest):
+//   G   (descending): thirds d0 = 0 and 2 need only the three inner register
+//       axes, after which they are final; third 1 then takes
+//       (p1 - p0) - p2 across the thirds, reading third 0 back from LDS.
+//   G^T (ascending):  d0 comes first: thirds 0 and 2 subtract third 1, then
+//       every third takes the three inner register axes.
+// Each third crosses to the wave part through three LDS sub-round buffers
+// ([3][tW][9][64]); third 1 is loaded while the first third is being stored.
+// Every entry sees the same operations in the same order as in inv_tile.
+template <typename T, int mW, bool ADJ, bool IN_PLACE>
+__device__ __forceinline__ void inv_tile_r4(const T* src, T* dst, uint64_t L, uint32_t hi, uint32_t j, int wave,
+                                            T* S)
+{
+    constexpr int tR = 81, TH = 27, tW = pow3c(mW), TM = tR * tW;
+    constexpr int SG = 9;                       // register indices per sub-round
+    constexpr int Q = (SG + tW - 1) / tW;       // register indices per wave per sub-round
+    constexpr int BUF = tW * SG * 64;           // elements per sub-round buffer
+    const int lane = threadIdx.x & 63;
+    const int gW1 = wave;
+    const uint64_t lo_w = (uint64_t)j * 64;
+    const uint32_t col_off = (uint32_t)lane * (uint32_t)sizeof(T);
+    const uint32_t seg_bytes = (uint32_t)((L - lo_w < 64 ? L - lo_w : 64) * sizeof(T));
+    const uint64_t row_bytes = L * sizeof(T);
+    const uint64_t tile_off = ((uint64_t)hi * TM * L + lo_w) * sizeof(T);
+    const char* s_tile = reinterpret_cast<const char*>(src) + tile_off;
+    char* d_tile = reinterpret_cast<char*>(dst) + tile_off;
+    // phase-1 rows of this wave: forward gW1*tR + gR, adjoint gR*tW + gW1
+    const char* s_wave = s_tile + (uint64_t)(ADJ ? gW1 : gW1 * tR) * row_bytes;
+    const uint64_t s_step = (ADJ ? (uint64_t)tW : 1ull) * row_bytes;
+    // LDS byte offsets; each base is opaque so that the accesses from it use
+    // immediate offsets (at most 64 KiB past the base)
+    char* Sc = reinterpret_cast<char*>(S);
+    auto lds_at = [&](uint32_t base, uint32_t off) -> T& { return *reinterpret_cast<T*>(Sc + base + off); };
+
+    auto load_third = [&](T (&t)[TH], int d0) {
+        const char* rp = s_wave + (uint64_t)(d0 * TH) * s_step;
+#pragma unroll
+        for (int i = 0; i < TH; ++i) {
+            t[i] = buf_load<T>(row_rsrc(rp, seg_bytes), col_off);
+            rp += s_step;
+        }
+    };
+    // register index d0*27 + i goes to buffer i / 9, entry (gW1*9 + i%9)
+    auto own_base = [&](int buf) {
+        return opaque_u32((uint32_t)((buf * BUF + gW1 * SG * 64 + lane) * sizeof(T)));
+    };
+    auto put_third = [&](const T (&t)[TH]) {
+        const uint32_t b01 = own_base(0), b2 = own_base(2);
+#pragma unroll
+        for (int i = 0; i < TH; ++i) {
+            const uint32_t o = (uint32_t)(((i / SG) % 2 * BUF + (i % SG) * 64) * sizeof(T));
+            lds_at(i / SG == 2 ? b2 : b01, o) = t[i];
+        }
+    };
+    // the wave part for the third d0 held in the buffers, then the stores
+    auto wave_part = [&](auto d0c) {
+        constexpr int d0 = decltype(d0c)::value;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int k = gW1 * Q + q;  // register index within a sub-round: digits d2 d3
+            if (k < SG) {
+                const bool k_one = (k % 3 == 1) || (k / 3 == 1);
+                const bool k_all = (k % 3 == 1) && (k / 3 == 1);
+#pragma unroll
+                for (int sr = 0; sr < 3; ++sr) {  // digit d1
+                    const uint32_t rb = opaque_u32((uint32_t)((sr * BUF + k * 64 + lane) * sizeof(T)));
+                    T u[tW];
+#pragma unroll
+                    for (int gW = 0; gW < tW; ++gW) u[gW] = lds_at(rb, (uint32_t)(gW * SG * 64 * sizeof(T)));
+                    if constexpr (ADJ) inv_adj_group<T, mW>(u);
+                    else inv_group<T, mW>(u);
+                    const int gR = d0 * TH + sr * SG + k;
+                    char* wp = d_tile + (uint64_t)(ADJ ? gR * tW : gR) * row_bytes;
+                    const uint64_t step = (ADJ ? 1ull : (uint64_t)tR) * row_bytes;
+#pragma unroll
+                    for (int gW = 0; gW < tW; ++gW) {
+                        bool changed;
+                        if constexpr (ADJ)
+                            changed = !(d0 == 1 && sr == 1 && k_all && all_digits_one(gW, mW));
+                        else
+                            changed = d0 == 1 || sr == 1 || k_one || has_digit_one(gW, mW);
+                        if (changed || !IN_PLACE) buf_store<T>(row_rsrc(wp, seg_bytes), col_off, u[gW]);
+                        wp += step;
+                    }
+                }
+            }
+        }
+    };
+    using D0 = std::integral_constant<int, 0>;
+    using D1 = std::integral_constant<int, 1>;
+    using D2 = std::integral_constant<int, 2>;
+
+    if constexpr (!ADJ) {
+        T a[TH], c[TH];
+        load_third(a, 0);
+        load_third(c, 2);
+        inv_group<T, 3>(a);
+        inv_group<T, 3>(c);
+        put_third(a);
+        // the third load may not move above the first third's arithmetic:
+        // three live thirds would not fit the register budget
+        __builtin_amdgcn_sched_barrier(0);
+        T b[TH];
+        load_third(b, 1);
+        lds_barrier();
+        wave_part(D0{});
+        inv_group<T, 3>(b);
+        {
+            const uint32_t b01 = own_base(0), b2 = own_base(2);
+#pragma unroll
+            for (int i = 0; i < TH; ++i) {
+                const uint32_t o = (uint32_t)(((i / SG) % 2 * BUF + (i % SG) * 64) * sizeof(T));
+                b[i] = (b[i] - lds_at(i / SG == 2 ? b2 : b01, o)) - c[i];
+            }
+        }
+        lds_barrier();
+        put_third(b);
+        lds_barrier();
+        wave_part(D1{});
+        lds_barrier();
+        put_third(c);
+        lds_barrier();
+        wave_part(D2{});
+    } else {
+        T a[TH], b[TH];
+        load_third(a, 0);
+        load_third(b, 1);
+#pragma unroll
+        for (int i = 0; i < TH; ++i) a[i] = a[i] - b[i];
+        inv_adj_group<T, 3>(a);
+        put_third(a);
+        // the third load may not move above the first third's arithmetic:
+        // three live thirds would not fit the register budget
+        __builtin_amdgcn_sched_barrier(0);
+        T c[TH];
+        load_third(c, 2);
+        lds_barrier();
+        wave_part(D0{});
+#pragma unroll
+        for (int i = 0; i < TH; ++i) c[i] = c[i] - b[i];
+        inv_adj_group<T, 3>(b);
+        inv_adj_group<T, 3>(c);
+        lds_barrier();
+        put_third(b);
+        lds_barrier();
+        wave_part(D1{});
+        lds_barrier();
+        put_third(c);
+        lds_barrier();
+        wave_part(D2{});
+    }
+}
+
+template <typename T, int mR, int mW, int CW, bool ADJ, bool IN_PLACE>
 __global__ __launch_bounds__(64 * pow3c(mW) * CW) void k_inv_pass(const T* src, T* dst, BMap src_map,
                                                                  BMap dst_map, uint64_t L, uint32_t tiles_per_hi,
                                                                  uint32_t n_tiles)
@@ -364,14 +521,22 @@ __global__ __launch_bounds__(64 * pow3c(mW) * CW) void k_inv_pass(const T* src, 
     __shared__ T S[P::LDS > 0 ? P::LDS : 1];
     src += src_map.at(blockIdx.y);
     dst += dst_map.at(blockIdx.y);
-    const bool in_place = (src == dst);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const TileWalk walk = xcd_tile_walk(n_tiles);
-    for (uint32_t t = walk.first; t < walk.end; t += walk.step) {
-        const uint32_t hi = t / tiles_per_hi;
-        const uint32_t j = t - hi * tiles_per_hi;
-        if constexpr (mW > 0) lds_barrier();  // the previous tile's phase-2 reads are done
-        inv_tile<T, mR, mW, CW, ADJ, true>(src, dst, L, hi, j, in_place, wave, S);
+    if constexpr (P::THIRDS) {
+        // launched with one tile per workgroup: no loop, so nothing tile-
+        // invariant is kept live across the register-heavy body
+        if (walk.first < walk.end) {
+            const uint32_t hi = walk.first / tiles_per_hi;
+            inv_tile_r4<T, mW, ADJ, IN_PLACE>(src, dst, L, hi, walk.first - hi * tiles_per_hi, wave, S);
+        }
+    } else {
+        for (uint32_t t = walk.first; t < walk.end; t += walk.step) {
+            const uint32_t hi = t / tiles_per_hi;
+            const uint32_t j = t - hi * tiles_per_hi;
+            if constexpr (mW > 0) lds_barrier();  // the previous tile's phase-2 reads are done
+            inv_tile<T, mR, mW, CW, ADJ, IN_PLACE, true>(src, dst, L, hi, j, wave, S);
+        }
     }
 }
 
