@@ -80,6 +80,8 @@ def _load():
     lib.hco_correlation_at_f64.restype = None
     lib.hco_bound_f64.argtypes = [P, P, P, I]
     lib.hco_bound_f64.restype = I
+    lib.hco_bound_at_f64.argtypes = [P, P, I, P, I64, P]
+    lib.hco_bound_at_f64.restype = I
     lib.hco_adjoint_bound_f64.argtypes = [P, P, P, P, P, I]
     lib.hco_adjoint_bound_f64.restype = I
     _lib = lib
@@ -206,6 +208,21 @@ def bound(x, y) -> np.ndarray:
     b = np.empty(3 ** D, dtype=np.float64)
     _load().hco_bound_f64(_ptr(x), _ptr(y), _ptr(b), D)
     return b
+
+
+def bound_at(x, y, ks) -> np.ndarray:
+    """bound() at selected output indices (each with at most 14 digits equal
+    to 1), without forming the whole 3^D array."""
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    x, y, D, _ = _pair(x, y)
+    ks = np.ascontiguousarray(ks, dtype=np.uint64).reshape(-1)
+    if ks.size and int(ks.max()) >= 3 ** D:
+        raise ValueError("output index out of range")
+    out = np.empty(ks.size, dtype=np.float64)
+    if _load().hco_bound_at_f64(_ptr(x), _ptr(y), D, _ptr(ks), ks.size, _ptr(out)):
+        raise ValueError("bound_at: an index has more than 14 digits equal to 1")
+    return out
 
 
 def adjoint_bound(x, y, w):

@@ -204,6 +204,53 @@ int hco_bound_f64(const double* x, const double* y, double* b, int D)
     return 0;
 }
 
+/* The same bound at single output indices, for sizes where the whole array
+ * would not fit.  B is a tensor product over the axes: where k has digit 0
+ * (or 2) it selects bit 0 (or 1) of both inputs on that axis, so B[k] equals
+ * the bound of the two sub-cubes spanned by the s axes where k has digit 1
+ * (the other bits fixed), taken at that sub-cube's all-ones index.  Returns
+ * 1 without writing when some index has more than 14 digits equal to 1. */
+int hco_bound_at_f64(const double* x, const double* y, int D, const uint64_t* ks, int64_t n, double* out)
+{
+    if (D < 0 || D > 40) return 1;
+    for (int64_t r = 0; r < n; ++r) {
+        uint64_t k = ks[r];
+        int s = 0;
+        for (int d = 0; d < D; ++d, k /= 3) s += (k % 3 == 1);
+        if (s > 14) return 1;
+    }
+    for (int64_t r = 0; r < n; ++r) {
+        uint64_t k = ks[r];
+        uint64_t base = 0;
+        int ones_bits[64];
+        int s = 0;
+        for (int d = 0; d < D; ++d) {
+            const uint64_t digit = k % 3;
+            k /= 3;
+            if (digit == 2) base |= (uint64_t)1 << d;
+            else if (digit == 1) ones_bits[s++] = d;
+        }
+        /* sub-cube index: its bit s-1-b (axis b of the sub-cube, most
+         * significant first) is the input bit ones_bits[s-1-b] */
+        const uint64_t m = (uint64_t)1 << s;
+        double* sx = (double*)malloc(2 * m * sizeof(double));
+        double* b = (double*)malloc(hco_pow3(s) * sizeof(double));
+        if (!sx || !b) abort();
+        for (uint64_t q = 0; q < m; ++q) {
+            uint64_t i = base;
+            for (int c = 0; c < s; ++c)
+                if ((q >> c) & 1u) i |= (uint64_t)1 << ones_bits[c];
+            sx[q] = x[i];
+            sx[m + q] = y[i];
+        }
+        hco_bound_rec(sx, sx + m, b, s);
+        out[r] = b[(hco_pow3(s) - 1) / 2];
+        free(sx);
+        free(b);
+    }
+    return 0;
+}
+
 /* Magnitude bounding the rounding error of the transposed-map adjoint:
  *   Bx = |F^T|(|G^T| |w| . F|y|),  By = |F^T|(|G^T| |w| . F|x|)
  * with |G^T|: (w0, w1, w2) -> (w0 + w1, w1, w2 + w1); same axis orders as the

@@ -1,0 +1,201 @@
+"""GPU parity at the benchmark workloads' full sizes, in the launch
+configuration the benchmark times (default plans, tuned batched plans).
+
+  D=16 int64     every output bitwise against Algorithm 1 (the naive
+                 Cartesian product) and the recursion
+  D=16 float64   every output bitwise against the canonical per-axis method;
+                 sampled outputs within the derived rounding bound of the
+                 compensated definition sum
+  D=20 float64   every output (3^20 = 3.49e9) bitwise against the canonical
+                 method (the recursion on 16 host threads), compared in
+                 chunks; sampled outputs within the bound of the definition
+  batched        4096 pairs, D uniform in {6..14}, float64 and float32, tuned
+                 plans: sampled pairs bitwise against the oracle, every pair
+                 bitwise against single-pair calls
+  backward       64 pairs at D=16, loss sum(w * z): sampled pairs bitwise
+                 against the transposed maps, sampled coordinates within the
+                 bound of the direct correlation, central differences
+"""
+import sys
+import time
+
+import numpy as np
+import pytest
+import torch
+
+import hc_inputs
+import oracle
+import paper_1608_00206_amd as hc
+from tests import pins
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+DEV = torch.device("cuda:0")
+U64 = 2.0 ** -53
+
+
+def say(msg):
+    print(f"[fullsize] {msg}", file=sys.stderr, flush=True)
+
+
+def on_gpu(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def sample_indices(D, n, seed, max_ones=14):
+    """n distinct output indices, uniform over 3^D, keeping those with at most
+    max_ones digits equal to 1 (the per-index bound's limit; at D = 20 that
+    drops about 0.2% of a uniform sample), plus the two corners."""
+    g = np.random.default_rng([hc_inputs.SEED, 77, seed, D])
+    ks = g.integers(0, 3 ** D, 4 * n, dtype=np.uint64)
+    keep = [int(k) for k in ks if sum(d == 1 for d in pins.ternary_digits(int(k), D)) <= max_ones]
+    out = np.unique(np.array(keep[:n] + [0, 3 ** D - 1], dtype=np.uint64))
+    return out
+
+
+def check_against_definition(x, y, z_at, ks, D):
+    """|z - definition| <= (4D+2) u B at the sampled indices (plus the
+    compensated sum's own rounding)."""
+    ref = oracle.direct_at(x, y, ks)
+    B = oracle.bound_at(x, y, ks)
+    tol = (4 * D + 2) * U64 * B + 2.0 ** -60 * np.abs(ref)
+    err = np.abs(z_at - ref)
+    assert np.all(err <= tol), f"max err/tol {np.max(err / np.maximum(tol, 1e-300))}"
+    return float(np.max(err / np.maximum(B, 1e-300)) / U64)
+
+
+def test_d16_int64_matches_algorithm1():
+    D = 16
+    x, y = hc_inputs.pair_ints(D, hc_inputs.W_D16)
+    say("D=16 int64: GPU")
+    z = hc.convolve(on_gpu(x), on_gpu(y))
+    torch.cuda.synchronize(DEV)
+    z = z.cpu().numpy()
+    t0 = time.time()
+    ref = oracle.naive(x, y)
+    say(f"D=16 int64: Algorithm 1 on the host in {time.time() - t0:.1f} s")
+    pins.assert_bitwise(z, ref, "D=16 int64 vs Algorithm 1")
+    pins.assert_bitwise(z, oracle.recursive(x, y, threads=16), "D=16 int64 vs recursion")
+
+
+def test_d16_f64_matches_canonical_and_definition():
+    D = 16
+    x, y = hc_inputs.pair_masses(D, hc_inputs.W_D16)
+    z = hc.convolve(on_gpu(x), on_gpu(y))
+    torch.cuda.synchronize(DEV)
+    z = z.cpu().numpy()
+    pins.assert_bitwise(z, oracle.canonical(x, y), "D=16 float64 vs canonical")
+    ks = sample_indices(D, 4096, 1)
+    r = check_against_definition(x, y, z[ks.astype(np.int64)], ks, D)
+    say(f"D=16 float64: max |err|/(u B) over {ks.size} sampled outputs = {r:.2f}")
+
+
+def test_d20_f64_every_output_bitwise():
+    D = 20
+    n3 = 3 ** D
+    x, y = hc_inputs.pair_masses(D, hc_inputs.W_D20_F64)
+    say("D=20 float64: GPU")
+    z_gpu = hc.convolve(on_gpu(x), on_gpu(y))
+    torch.cuda.synchronize(DEV)
+    t0 = time.time()
+    ref = oracle.recursive(x, y, threads=16)
+    say(f"D=20 float64: oracle recursion in {time.time() - t0:.1f} s; comparing")
+    chunk = 1 << 28
+    mismatches = 0
+    for c0 in range(0, n3, chunk):
+        c1 = min(n3, c0 + chunk)
+        part = z_gpu[c0:c1].cpu().numpy()
+        mismatches += int(np.count_nonzero(part.view(np.uint64) != ref[c0:c1].view(np.uint64)))
+    say(f"D=20 float64: {mismatches} of {n3} outputs differ")
+    assert mismatches == 0
+    ks = sample_indices(D, 256, 2)
+    z_at = z_gpu[torch.from_numpy(ks.astype(np.int64)).to(DEV)].cpu().numpy()
+    r = check_against_definition(x, y, z_at, ks, D)
+    say(f"D=20 float64: max |err|/(u B) over {ks.size} sampled outputs = {r:.2f}")
+    del z_gpu, ref
+    torch.cuda.empty_cache()
+
+
+@pytest.fixture(scope="module")
+def batched_config():
+    Ds = [int(d) for d in hc_inputs.batched_dims(4096)]
+    return Ds
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_batched_4096_pairs(batched_config, dtype):
+    Ds = batched_config
+    npdt = np.float64 if dtype == torch.float64 else np.float32
+    say(f"batched {dtype}: tuning a plan for {len(Ds)} pairs")
+    with hc.BatchedPlan(Ds, dtype=dtype, tune=True) as plan:
+        xs, ys = [], []
+        for p, D in enumerate(Ds):
+            x, y = hc_inputs.pair_masses(D, hc_inputs.W_BATCHED, p, dtype=npdt)
+            xs.append(x)
+            ys.append(y)
+        X = on_gpu(np.concatenate(xs))
+        Y = on_gpu(np.concatenate(ys))
+        Z = plan.run(X, Y)
+        plan.check()
+        xo, zo = plan.x_offsets, plan.z_offsets
+        # every pair against the single-pair entry point
+        for p in range(len(Ds)):
+            zs = hc.convolve(X[xo[p]:xo[p + 1]], Y[xo[p]:xo[p + 1]])
+            if not torch.equal(zs.view(torch.int64 if npdt == np.float64 else torch.int32),
+                               Z[zo[p]:zo[p + 1]].view(torch.int64 if npdt == np.float64 else torch.int32)):
+                raise AssertionError(f"pair {p} (D={Ds[p]}) differs from the single-pair call")
+        torch.cuda.synchronize(DEV)
+        # sampled pairs against the oracle: every D, the largest pairs first
+        by_d = {}
+        for p, D in enumerate(Ds):
+            by_d.setdefault(D, []).append(p)
+        sample = sorted(q for D in by_d for q in by_d[D][:3])
+        worst = 0.0
+        for p in sample:
+            z = Z[zo[p]:zo[p + 1]].cpu().numpy()
+            pins.assert_bitwise(z, oracle.canonical(xs[p], ys[p]), f"pair {p} D={Ds[p]}")
+            if npdt == np.float32:
+                z64 = oracle.canonical(xs[p].astype(np.float64), ys[p].astype(np.float64))
+                worst = max(worst, float(np.max(np.abs(z - z64)) / np.max(np.abs(z64))))
+        if npdt == np.float32:
+            # reported, not gated: float32 against the float64 oracle
+            say(f"batched float32 vs float64 oracle: max error / max|z| = {worst:.3g}")
+
+
+def test_backward_64_pairs_d16():
+    D, B = 16, 64
+    xs = np.stack([hc_inputs.pair_masses(D, hc_inputs.W_BACKWARD, p)[0] for p in range(B)])
+    ys = np.stack([hc_inputs.pair_masses(D, hc_inputs.W_BACKWARD, p)[1] for p in range(B)])
+    X, Y = on_gpu(xs), on_gpu(ys)
+    W = torch.empty((B, 3 ** D), dtype=torch.float64, device=DEV)
+    for p in range(B):
+        W[p] = on_gpu(hc_inputs.loss_weights(D, hc_inputs.W_BACKWARD, p))
+    gx, gy = hc.convolve_backward(X, Y, W)
+    torch.cuda.synchronize(DEV)
+    gx, gy = gx.cpu().numpy(), gy.cpu().numpy()
+    for p in (0, 21, 63):
+        w = W[p].cpu().numpy()
+        ox, oy = oracle.adjoint(xs[p], ys[p], w)
+        pins.assert_bitwise(gx[p], ox, f"grad_x pair {p}")
+        pins.assert_bitwise(gy[p], oy, f"grad_y pair {p}")
+        idx = np.random.default_rng([hc_inputs.SEED, 78, p]).integers(0, 1 << D, 256).astype(np.uint64)
+        cx, cy = oracle.correlation_at(xs[p], ys[p], w, idx)
+        bx, by = oracle.adjoint_bound(xs[p], ys[p], w)
+        ii = idx.astype(np.int64)
+        tol = (4 * D + 2) * U64
+        assert np.all(np.abs(gx[p][ii] - cx) <= tol * bx[ii] + 2.0 ** -60 * np.abs(cx))
+        assert np.all(np.abs(gy[p][ii] - cy) <= tol * by[ii] + 2.0 ** -60 * np.abs(cy))
+    # central differences of L = sum(w * z) on the GPU forward: L is bilinear,
+    # so the difference quotient has no truncation error, only rounding
+    p = 5
+    w = W[p]
+    x0 = X[p].clone()
+    h = 1e-6
+    scale = float(np.max(np.abs(gx[p])))
+    for i in np.random.default_rng([hc_inputs.SEED, 79]).integers(0, 1 << D, 32):
+        xp = x0.clone(); xp[i] += h
+        xm = x0.clone(); xm[i] -= h
+        lp = torch.dot(hc.convolve(xp, Y[p]), w).item()
+        lm = torch.dot(hc.convolve(xm, Y[p]), w).item()
+        fd = (lp - lm) / (2 * h)
+        assert abs(fd - gx[p][i]) <= 1e-6 * scale, (i, fd, gx[p][i])

@@ -153,6 +153,20 @@ def test_mass_inputs_within_bound_vs_direct(D):
     assert np.all(np.abs(z - ref) <= tol)
 
 
+@pytest.mark.parametrize("D", [0, 1, 5, 8])
+def test_bound_at_matches_full_bound(D):
+    """The per-index bound (sub-cube of the digit-1 axes) equals the full
+    bound array everywhere; indices with too many 1 digits are refused."""
+    g = np.random.default_rng([53, D])
+    x = g.uniform(-1, 1, 1 << D)
+    y = g.uniform(-1, 1, 1 << D)
+    ks = np.arange(3 ** D, dtype=np.uint64)
+    assert np.array_equal(oracle.bound_at(x, y, ks), oracle.bound(x, y))
+    if D >= 1:
+        with pytest.raises(ValueError):
+            oracle.bound_at(np.ones(1 << 15), np.ones(1 << 15), [(3 ** 15 - 1) // 2])
+
+
 def test_tern_map():
     g = pins.golden("carry_free_example.json")
     assert oracle.tern(g["i"]) + oracle.tern(g["j"]) == g["k_flat"]
