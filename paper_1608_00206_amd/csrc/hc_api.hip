@@ -171,8 +171,7 @@ Plan make_plan(int D, int dtype, const PlanOpts& o)
     P.D = D;
     P.dtype = dtype;
     P.esize = dtype_size(dtype);
-    // the adjoint tile also keeps x and y in LDS beside w_hat: at most 8 axes
-    const int kmax = o.backward ? cmin(8, max_fused_depth(dtype)) : max_fused_depth(dtype);
+    const int kmax = max_fused_depth(dtype);
     int K = o.fused_depth > 0 ? o.fused_depth : kmax;
     if (K > kmax) K = kmax;
     if (K > D) K = D;
@@ -221,10 +220,9 @@ Plan make_plan(int D, int dtype, const PlanOpts& o)
     return P;
 }
 
-PlanOpts default_opts(bool backward)
+PlanOpts default_opts()
 {
     PlanOpts o;
-    o.backward = backward;
     if (const char* s = getenv("HC_FUSED_K")) o.fused_depth = atoi(s);
     if (const char* s = getenv("HC_INV_MAXM")) o.inv_group_max = atoi(s);
     if (const char* s = getenv("HC_INV_REG")) o.inv_reg = atoi(s);
@@ -395,6 +393,12 @@ int launch_fused_adj(int K, const T* xt, const T* yt, const T* w, T* gxt, T* gyt
         case 6: launch_fused_adj_k<T, 6>(xt, yt, w, gxt, gyt, in_bs, w_bs, g_bs, n_tiles, batch, cus, per_cu, s); break;
         case 7: launch_fused_adj_k<T, 7>(xt, yt, w, gxt, gyt, in_bs, w_bs, g_bs, n_tiles, batch, cus, per_cu, s); break;
         case 8: launch_fused_adj_k<T, 8>(xt, yt, w, gxt, gyt, in_bs, w_bs, g_bs, n_tiles, batch, cus, per_cu, s); break;
+        case 9:
+            if constexpr (sizeof(T) == 4) {
+                launch_fused_adj_k<T, 9>(xt, yt, w, gxt, gyt, in_bs, w_bs, g_bs, n_tiles, batch, cus, per_cu, s);
+                break;
+            }
+            return fail(HC_ERR_UNSUPPORTED, "no adjoint fused tile of 9 axes for 8-byte elements");
         default: return fail(HC_ERR_UNSUPPORTED, "no adjoint fused tile of %d axes", K);
     }
     return HC_OK;
@@ -646,7 +650,7 @@ size_t hc_workspace_bytes(int D, int dtype, int batch)
 size_t hc_backward_workspace_bytes(int D, int dtype, int batch)
 {
     if (D < 0 || D > HC_MAX_D || dtype_size(dtype) == 0 || batch < 1) return (size_t)-1;
-    return plan_bwd_ws_bytes(make_plan(D, dtype, default_opts(true)), batch);
+    return plan_bwd_ws_bytes(make_plan(D, dtype, default_opts()), batch);
 }
 
 int hc_convolve_batch(const void* x, const void* y, void* z, int D, int dtype, int batch, void* workspace,
@@ -707,7 +711,7 @@ int hc_convolve_backward_batch(const void* x, const void* y, const void* grad_z,
     if (es == 0) return fail(HC_ERR_UNSUPPORTED, "unknown dtype %d", dtype);
     if (dtype == HC_I64) return fail(HC_ERR_UNSUPPORTED, "the backward pass supports float64 and float32 only");
     if (batch < 1 || batch > 65535) return fail(HC_ERR_INVALID_ARG, "batch=%d outside [1, 65535]", batch);
-    const Plan P = make_plan(D, dtype, default_opts(true));
+    const Plan P = make_plan(D, dtype, default_opts());
     if (grad_z_stride != 0 && (grad_z_stride < 0 || (uint64_t)grad_z_stride < P.n3))
         return fail(HC_ERR_INVALID_ARG, "grad_z_stride must be 0 or at least 3^D");
     if (misaligned(x, es) || misaligned(y, es) || misaligned(grad_z, es) || misaligned(grad_x, es) ||

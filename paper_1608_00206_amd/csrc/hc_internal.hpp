@@ -24,7 +24,6 @@ struct PlanOpts {
     int fused_depth = 0;     // K: inner axes fused in one tile
     int inv_group_max = 0;   // largest outer inverse group (at most 6)
     int inv_reg = 0;         // axes of a group held in registers (at most 4)
-    bool backward = false;   // plan for the adjoint kernels (fused depth <= 8)
     int grid_per_cu = 0;     // 0: one tile per workgroup; else at most this many workgroups per CU
 };
 
@@ -73,7 +72,7 @@ bool misaligned(const void* p, size_t align);
 int device_cus(int* cus);
 int max_fused_depth(int dtype);
 Plan make_plan(int D, int dtype, const PlanOpts& o);
-PlanOpts default_opts(bool backward = false);
+PlanOpts default_opts();
 size_t plan_ws_bytes(const Plan& P, int batch);
 size_t plan_bwd_ws_bytes(const Plan& P, int batch);
 

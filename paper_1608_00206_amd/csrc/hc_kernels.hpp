@@ -86,8 +86,6 @@ struct FusedCfg {
     static constexpr int R2h = nA * tC * tB;    // per operand
     static constexpr int FWD_LDS = 2 * (R0h + R1h + R2h);
     static constexpr int LDS = cmax(N3, FWD_LDS);
-    // backward: R2 (x, y) stays live next to the w_hat tile
-    static constexpr int ADJ_LDS = 2 * R2h + cmax(N3, 2 * (R0h + R1h));
 };
 
 // Forward half shared by the fused forward and the fused adjoint: loads the
@@ -577,16 +575,18 @@ __global__ __launch_bounds__(NT) void k_fwd_adj_pass(const T* __restrict__ in0, 
 
 // =========================================================================
 // Fused inner tile of the backward pass, for one outer index o:
-//   Q0  x~[o], y~[o] -> F on groups C, B (shared with the forward)      -> R2
 //   Q1  G^T on group C of w_hat[o] (thread per (gB, gA)), from global    -> W
 //   Q2  G^T on group B (thread per (gC, gA))                             W -> W
-//   Q3  G^T on group A; F on group A of x and y; gx_hat = w.y_hat,
+//   Q3  registers take this thread's W row (3^kA values); W is released
+//   Q0  x~[o], y~[o] -> F on groups C, B (shared with the forward)      -> R2
+//   Q3' G^T on group A; F on group A of x and y; gx_hat = w.y_hat,
 //       gy_hat = w.x_hat; F^T on group A  (thread per (gC, gB))         -> R2
 //   Q4  F^T on group B (thread per (gC, bA))                          R2 -> R1
 //   Q5  F^T on group C (thread per (bB, bA)), contiguous store of the
 //       2^K-entry rows gx~[o], gy~[o]
-// Either gradient row may be null (not requested).  lds holds
-// FusedCfg<K>::ADJ_LDS elements.
+// The w_hat tile and the x, y stages never share LDS at the same time, so
+// the tile needs no more LDS than the forward one (FusedCfg<K>::LDS).
+// Either gradient row may be null (not requested).
 // =========================================================================
 template <typename T, int K, int NT>
 __device__ __forceinline__ void fused_tile_adj(const T* __restrict__ xr, const T* __restrict__ yr,
@@ -594,15 +594,13 @@ __device__ __forceinline__ void fused_tile_adj(const T* __restrict__ xr, const T
                                                T* __restrict__ gyr, T* lds)
 {
     using C = FusedCfg<K>;
-    T* R2 = lds;                       // x2, y2, later gx2, gy2
-    T* U = lds + 2 * C::R2h;           // R0 + R1 during Q0, W from Q1, R1' in Q4
-    T* R0 = U;
-    T* R1 = U + 2 * C::R0h;
-    T* W = U;
+    T* W = lds;
+    T* R0 = lds;
+    T* R1 = R0 + 2 * C::R0h;
+    T* R2 = R1 + 2 * C::R1h;           // x2, y2, later gx2, gy2
     constexpr int N3I = C::tC * C::tB;
     constexpr int IPT = (N3I + NT - 1) / NT;
     const int tid = threadIdx.x;
-    fused_forward_cb<T, K, NT>(xr, yr, R0, R1, R2);
     // Q1: G^T on group C, straight from global memory
     for (int it = tid; it < C::tB * C::tA; it += NT) {
         T v[pow3c(C::kC)];
@@ -628,31 +626,34 @@ __device__ __forceinline__ void fused_tile_adj(const T* __restrict__ xr, const T
         }
         lds_barrier();
     }
-    // Q3: registers take this thread's W row and R2 columns; then R2 is reused
-    T wa[IPT][pow3c(C::kA)], xa[IPT][C::nA], ya[IPT][C::nA];
+    // Q3: registers take this thread's W row; then the forward half reuses W
+    T wa[IPT][pow3c(C::kA)];
 #pragma unroll
     for (int j = 0; j < IPT; ++j) {
         const int it = tid + j * NT;
         if (it < N3I) {
 #pragma unroll
             for (int g = 0; g < C::tA; ++g) wa[j][g] = W[it * C::tA + g];
-#pragma unroll
-            for (int bA = 0; bA < C::nA; ++bA) {
-                xa[j][bA] = R2[bA * N3I + it];
-                ya[j][bA] = R2[C::R2h + bA * N3I + it];
-            }
         }
     }
     lds_barrier();
+    fused_forward_cb<T, K, NT>(xr, yr, R0, R1, R2);
+    // Q3': each thread's R2 columns are read and rewritten by that thread only
 #pragma unroll
     for (int j = 0; j < IPT; ++j) {
         const int it = tid + j * NT;
         if (it < N3I) {
+            T xa[C::nA], ya[C::nA];
+#pragma unroll
+            for (int bA = 0; bA < C::nA; ++bA) {
+                xa[bA] = R2[bA * N3I + it];
+                ya[bA] = R2[C::R2h + bA * N3I + it];
+            }
             inv_adj_group<T, C::kA>(wa[j]);
             if (gyr) {
                 T s[pow3c(C::kA)];
 #pragma unroll
-                for (int bA = 0; bA < C::nA; ++bA) s[bA] = xa[j][bA];
+                for (int bA = 0; bA < C::nA; ++bA) s[bA] = xa[bA];
                 fwd_group<T, C::kA>(s);
 #pragma unroll
                 for (int g = 0; g < C::tA; ++g) s[g] = wa[j][g] * s[g];
@@ -663,7 +664,7 @@ __device__ __forceinline__ void fused_tile_adj(const T* __restrict__ xr, const T
             if (gxr) {
                 T s[pow3c(C::kA)];
 #pragma unroll
-                for (int bA = 0; bA < C::nA; ++bA) s[bA] = ya[j][bA];
+                for (int bA = 0; bA < C::nA; ++bA) s[bA] = ya[bA];
                 fwd_group<T, C::kA>(s);
 #pragma unroll
                 for (int g = 0; g < C::tA; ++g) s[g] = wa[j][g] * s[g];
@@ -711,7 +712,7 @@ __global__ __launch_bounds__(NT) void k_fused_inner_adj(const T* __restrict__ xt
                                                         BMap g_map, uint32_t n_tiles)
 {
     using C = FusedCfg<K>;
-    __shared__ T lds[C::ADJ_LDS];
+    __shared__ T lds[C::LDS];
     xt += in_map.at(blockIdx.y);
     yt += in_map.at(blockIdx.y);
     w += w_map.at(blockIdx.y);
