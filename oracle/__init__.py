@@ -62,7 +62,9 @@ def _load():
         for name, args in (("hco_naive_", [P, P, P, I]),
                            ("hco_canonical_", [P, P, P, I]),
                            ("hco_recursive_", [P, P, P, I, I]),
-                           ("hco_adjoint_", [P, P, P, P, P, I])):
+                           ("hco_adjoint_", [P, P, P, P, P, I]),
+                           ("hco_carryfree_naive_", [P, P, ctypes.c_uint64, P]),
+                           ("hco_difference_naive_", [P, P, P, I])):
             fn = getattr(lib, name + sfx)
             fn.argtypes = args
             fn.restype = I
@@ -159,6 +161,33 @@ def recursive(x, y, threads: int = 1, out: np.ndarray | None = None) -> np.ndarr
     if rc:
         raise RuntimeError(f"hco_recursive_{sfx} failed ({rc})")
     return out
+
+
+def carryfree_naive(x, y) -> np.ndarray:
+    """Carry-free convolution of two length-n vectors (any n >= 1) by its
+    definition; 3^D outputs, D = bits of n - 1."""
+    x = _vec(x)
+    y = _vec(y)
+    if x.dtype != y.dtype or x.size != y.size or x.size == 0:
+        raise ValueError("x and y must be non-empty vectors of one length and dtype")
+    n = x.size
+    D = max(0, (n - 1).bit_length())
+    z = np.empty(3 ** D, dtype=x.dtype)
+    rc = getattr(_load(), "hco_carryfree_naive_" + _SFX[x.dtype])(_ptr(x), _ptr(y), n, _ptr(z))
+    if rc:
+        raise RuntimeError(f"hco_carryfree_naive failed ({rc})")
+    return z
+
+
+def difference_naive(x, y) -> np.ndarray:
+    """Distribution of X - Y by its definition: output digit a is
+    bit_a(i) - bit_a(j) + 1."""
+    x, y, D, sfx = _pair(x, y)
+    z = np.empty(3 ** D, dtype=x.dtype)
+    rc = getattr(_load(), "hco_difference_naive_" + sfx)(_ptr(x), _ptr(y), _ptr(z), D)
+    if rc:
+        raise RuntimeError(f"hco_difference_naive_{sfx} failed ({rc})")
+    return z
 
 
 def adjoint(x, y, w):

@@ -16,6 +16,8 @@
  *   hco_canonical_*  the method, per-axis form, full-size scratch
  *   hco_recursive_*  the method, three-subproblem recursion, memory-light
  *   hco_adjoint_*    transposed maps (gradient of sum(w * z))
+ *   hco_carryfree_naive_*   carry-free 1-D convolution by its definition
+ *   hco_difference_naive_*  distribution of X - Y by its definition
  * plus fp64/long double helpers for pins: the ternary index map, the direct
  * per-element definition sum, the direct correlation gradient and the
  * rounding-error bound.

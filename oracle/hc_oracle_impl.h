@@ -235,6 +235,41 @@ int HCO_FN(hco_adjoint_)(const ELEM* x, const ELEM* y, const ELEM* w,
     return 0;
 }
 
+/* Carry-free convolution of two length-n vectors (Discussion): indices are
+ * added bit by bit without carries, so x[i] * y[j] belongs to the output
+ * whose base-3 digits are the digit-wise sums of the bits of i and j.  The
+ * output has 3^D entries, D the number of bits of n - 1 (D = 0 for n = 1).
+ * Written over the 1-D indices directly: i outer loop, j inner loop. */
+int HCO_FN(hco_carryfree_naive_)(const ELEM* x, const ELEM* y, uint64_t n, ELEM* z)
+{
+    if (n == 0 || n > ((uint64_t)1 << 20)) return 1;
+    int D = 0;
+    while (((uint64_t)1 << D) < n) ++D;
+    const uint64_t n3 = hco_pow3(D);
+    for (uint64_t k = 0; k < n3; ++k) z[k] = (ELEM)0;
+    for (uint64_t i = 0; i < n; ++i)
+        for (uint64_t j = 0; j < n; ++j)
+            z[hco_tern(i) + hco_tern(j)] += x[i] * y[j];
+    return 0;
+}
+
+/* Distribution of the difference of two random vectors with values in
+ * {0,1}^D (Introduction: probability mass functions of sums and differences).
+ * Output digit a holds bit_a(i) - bit_a(j) + 1 in {0, 1, 2}, i.e. x[i] * y[j]
+ * belongs to z[tern(i) - tern(j) + (3^D - 1) / 2].  i outer, j inner. */
+int HCO_FN(hco_difference_naive_)(const ELEM* x, const ELEM* y, ELEM* z, int D)
+{
+    if (D < 0 || D > 20) return 1;
+    const uint64_t n2 = (uint64_t)1 << D;
+    const uint64_t n3 = hco_pow3(D);
+    const uint64_t mid = (n3 - 1) / 2;
+    for (uint64_t k = 0; k < n3; ++k) z[k] = (ELEM)0;
+    for (uint64_t i = 0; i < n2; ++i)
+        for (uint64_t j = 0; j < n2; ++j)
+            z[hco_tern(i) + mid - hco_tern(j)] += x[i] * y[j];
+    return 0;
+}
+
 #undef HCO_FN
 #undef HCO_CAT
 #undef HCO_CAT2
