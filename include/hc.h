@@ -230,6 +230,45 @@ int hc_plan_inspect(const int* Ds, int n_pairs, int dtype, unsigned flags, int64
                     int64_t* n_groups);
 
 /*
+ * Carry-free convolution of two vectors (Discussion: embedding a 1-D
+ * problem in a hypercube).  With D = ceil(log2 n) bits per index, x[i] * y[j]
+ * is added to z[k] where k's base-3 digits are the digit-wise sums of the
+ * bits of i and j (no carries): k = hc_carryfree_index(i, j).  Entries of the
+ * vectors past n are taken as zero (the hypercubes are zero-padded to 2^D).
+ *   x, y        device, n elements each (read only), 1 <= n <= 2^HC_MAX_D
+ *   z           device, 3^D elements (written); D = hc_carryfree_dim(n)
+ *   workspace   hc_carryfree_workspace_bytes(n, dtype) bytes: the padded
+ *               copies (when n is not a power of two) and the convolution's
+ *               own workspace
+ * Results are bitwise those of hc_convolve on the zero-padded vectors.
+ * Errors: as hc_convolve; HC_ERR_D_RANGE for n outside the range.
+ */
+int hc_carryfree_dim(uint64_t n);                       /* -1 if n is out of range */
+uint64_t hc_carryfree_index(uint64_t i, uint64_t j);    /* output index of x[i] * y[j] */
+size_t hc_carryfree_workspace_bytes(uint64_t n, int dtype);  /* (size_t)-1 if invalid */
+int hc_carryfree_convolve(const void* x, const void* y, uint64_t n, void* z, int dtype, void* workspace,
+                          size_t workspace_bytes, hipStream_t stream);
+
+/*
+ * Distribution of the difference X - Y of independent random vectors with
+ * values in {0,1}^D (Introduction: distributions of sums and differences;
+ * the sum X + Y is hc_convolve itself), for `batch` pairs:
+ *   z[b][k] = sum over i, j with bit_a(i) - bit_a(j) = digit_a(k) - 1 on
+ *             every axis a of x[b][i] * y[b][j]
+ * so digit 0, 1, 2 of k stands for a difference of -1, 0, +1 on that axis.
+ * Computed as the convolution of x with y reflected on every axis (each bit
+ * b replaced by 1 - b), which the workspace holds.
+ *   x, y        device, batch x 2^D elements (read only)
+ *   z           device, batch x 3^D elements (written)
+ *   workspace   hc_difference_workspace_bytes(D, dtype, batch) bytes
+ * Results are bitwise those of hc_convolve_batch on (x, reflected y).
+ * Errors: as hc_convolve_batch.
+ */
+size_t hc_difference_workspace_bytes(int D, int dtype, int batch);  /* (size_t)-1 if invalid */
+int hc_difference_batch(const void* x, const void* y, void* z, int D, int dtype, int batch, void* workspace,
+                        size_t workspace_bytes, hipStream_t stream);
+
+/*
  * Kernel profiler (measurement support; not part of the method).
  * While enabled, every kernel launch of the calling process is bracketed by
  * a pair of HIP events recorded on the launch stream, and tagged with the

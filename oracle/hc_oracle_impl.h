@@ -247,9 +247,10 @@ int HCO_FN(hco_carryfree_naive_)(const ELEM* x, const ELEM* y, uint64_t n, ELEM*
     while (((uint64_t)1 << D) < n) ++D;
     const uint64_t n3 = hco_pow3(D);
     for (uint64_t k = 0; k < n3; ++k) z[k] = (ELEM)0;
-    for (uint64_t i = 0; i < n; ++i)
-        for (uint64_t j = 0; j < n; ++j)
-            z[hco_tern(i) + hco_tern(j)] += x[i] * y[j];
+    for (uint64_t i = 0; i < n; ++i) {
+        const uint64_t ti = hco_tern(i);
+        for (uint64_t j = 0; j < n; ++j) z[ti + hco_tern(j)] += x[i] * y[j];
+    }
     return 0;
 }
 
@@ -264,9 +265,10 @@ int HCO_FN(hco_difference_naive_)(const ELEM* x, const ELEM* y, ELEM* z, int D)
     const uint64_t n3 = hco_pow3(D);
     const uint64_t mid = (n3 - 1) / 2;
     for (uint64_t k = 0; k < n3; ++k) z[k] = (ELEM)0;
-    for (uint64_t i = 0; i < n2; ++i)
-        for (uint64_t j = 0; j < n2; ++j)
-            z[hco_tern(i) + mid - hco_tern(j)] += x[i] * y[j];
+    for (uint64_t i = 0; i < n2; ++i) {
+        const uint64_t ti = hco_tern(i) + mid;
+        for (uint64_t j = 0; j < n2; ++j) z[ti - hco_tern(j)] += x[i] * y[j];
+    }
     return 0;
 }
 

@@ -25,7 +25,8 @@ from . import _abi
 from ._abi import HCError
 
 __all__ = ["convolve", "convolve_batch", "convolve_backward", "HypercubeConv", "HCError", "BatchedPlan",
-           "workspace_bytes", "backward_workspace_bytes", "dim_of", "DTYPES"]
+           "workspace_bytes", "backward_workspace_bytes", "dim_of", "DTYPES",
+           "carryfree_convolve", "carryfree_index", "carryfree_dim", "difference", "difference_batch"]
 
 DTYPES = {torch.float64: _abi.HC_F64, torch.float32: _abi.HC_F32, torch.int64: _abi.HC_I64}
 
@@ -162,6 +163,82 @@ def convolve_backward(x: torch.Tensor, y: torch.Tensor, grad_z: torch.Tensor, ne
         gx.data_ptr() if gx is not None else 0, gy.data_ptr() if gy is not None else 0,
         D, code, B, ws.data_ptr() if ws is not None else 0, nbytes, _stream(x.device)))
     return gx, gy
+
+
+def carryfree_dim(n: int) -> int:
+    """Bits per index (ceil(log2 n)) of the carry-free convolution of length-n vectors."""
+    D = _abi.hc_carryfree_dim(int(n))
+    if D < 0:
+        raise ValueError(f"length {n} out of range")
+    return D
+
+
+def carryfree_index(i: int, j: int) -> int:
+    """Output index of x[i] * y[j] in the carry-free convolution: the base-3
+    number whose digits are the bit-wise sums of i and j."""
+    return int(_abi.hc_carryfree_index(int(i), int(j)))
+
+
+def carryfree_convolve(x: torch.Tensor, y: torch.Tensor, out: torch.Tensor | None = None,
+                       workspace: torch.Tensor | None = None) -> torch.Tensor:
+    """Carry-free convolution of two 1-D tensors of equal length n (any n >= 1):
+    x[i] * y[j] is added to z[carryfree_index(i, j)]; returns 3^D values,
+    D = carryfree_dim(n)."""
+    if x.dim() != 1 or x.shape != y.shape:
+        raise ValueError("x and y must be 1-D tensors of the same length")
+    if x.dtype != y.dtype:
+        raise TypeError("x and y must have the same dtype")
+    _check_device(x, y)
+    n = x.numel()
+    D = carryfree_dim(n)
+    code = _dtype_code(x)
+    x = x.contiguous()
+    y = y.contiguous()
+    if out is None:
+        out = torch.empty(3 ** D, dtype=x.dtype, device=x.device)
+    elif out.numel() != 3 ** D or out.dtype != x.dtype or not out.is_contiguous() or out.device != x.device:
+        raise ValueError("out must be a contiguous tensor of 3^D elements of the input dtype")
+    nbytes = _abi.hc_carryfree_workspace_bytes(n, code)
+    ws = _workspace(nbytes, x.device, workspace)
+    _abi.check(_abi.hc_carryfree_convolve(x.data_ptr(), y.data_ptr(), n, out.data_ptr(), code,
+                                          ws.data_ptr() if ws is not None else 0, nbytes, _stream(x.device)))
+    return out
+
+
+def difference_batch(x: torch.Tensor, y: torch.Tensor, out: torch.Tensor | None = None,
+                     workspace: torch.Tensor | None = None) -> torch.Tensor:
+    """Distribution of X - Y for (B, 2^D) distributions x of X and y of Y
+    over {0,1}^D: digit 0, 1, 2 of an output index stands for a difference
+    of -1, 0, +1 on that axis.  Returns (B, 3^D)."""
+    if x.dim() != 2 or x.shape != y.shape:
+        raise ValueError("x and y must both have shape (B, 2^D)")
+    if x.dtype != y.dtype:
+        raise TypeError("x and y must have the same dtype")
+    _check_device(x, y)
+    B, n = x.shape
+    D = dim_of(n)
+    code = _dtype_code(x)
+    x = x.contiguous()
+    y = y.contiguous()
+    if out is None:
+        out = torch.empty((B, 3 ** D), dtype=x.dtype, device=x.device)
+    elif out.shape != (B, 3 ** D) or out.dtype != x.dtype or not out.is_contiguous() or out.device != x.device:
+        raise ValueError("out must be a contiguous (B, 3^D) tensor of the input dtype")
+    nbytes = _abi.hc_difference_workspace_bytes(D, code, B)
+    ws = _workspace(nbytes, x.device, workspace)
+    _abi.check(_abi.hc_difference_batch(x.data_ptr(), y.data_ptr(), out.data_ptr(), D, code, B,
+                                        ws.data_ptr() if ws is not None else 0, nbytes, _stream(x.device)))
+    return out
+
+
+def difference(x: torch.Tensor, y: torch.Tensor, out: torch.Tensor | None = None,
+               workspace: torch.Tensor | None = None) -> torch.Tensor:
+    """Single-pair form of difference_batch: (2^D,) inputs, (3^D,) output."""
+    if x.dim() != 1 or x.shape != y.shape:
+        raise ValueError("x and y must be 1-D tensors of the same length 2^D")
+    D = dim_of(x.numel())
+    flat = out.view(1, 3 ** D) if out is not None else None
+    return difference_batch(x.view(1, -1), y.view(1, -1), out=flat, workspace=workspace).view(3 ** D)
 
 
 class HypercubeConv(torch.autograd.Function):

@@ -66,6 +66,12 @@ SIGNATURES = {
     "hc_plan_describe": ([_P, ctypes.c_char_p, _SZ], _I),
     "hc_plan_inspect": ([ctypes.POINTER(_I), _I, _I, ctypes.c_uint, ctypes.POINTER(_I64), _I64,
                          ctypes.POINTER(_I64)], _I),
+    "hc_carryfree_dim": ([_U64], _I),
+    "hc_carryfree_index": ([_U64, _U64], _U64),
+    "hc_carryfree_workspace_bytes": ([_U64, _I], _SZ),
+    "hc_carryfree_convolve": ([_P, _P, _U64, _P, _I, _P, _SZ, _P], _I),
+    "hc_difference_workspace_bytes": ([_I, _I, _I], _SZ),
+    "hc_difference_batch": ([_P, _P, _P, _I, _I, _I, _P, _SZ, _P], _I),
     "hc_profile_enable": ([_I], _I),
     "hc_profile_collect": ([ctypes.POINTER(KernelStat), _I, ctypes.POINTER(_I)], _I),
 }
@@ -139,6 +145,31 @@ def hc_convolve_backward_batch(x: int, y: int, gz: int, gz_stride: int, gx: int,
 def hc_convolve_backward(x: int, y: int, gz: int, gx: int, gy: int, D: int, dtype: int, ws: int, ws_bytes: int,
                          stream: int) -> int:
     return lib().hc_convolve_backward(x, y, gz, gx, gy, D, dtype, ws, ws_bytes, stream)
+
+
+def hc_carryfree_dim(n: int) -> int:
+    return lib().hc_carryfree_dim(n)
+
+
+def hc_carryfree_index(i: int, j: int) -> int:
+    return lib().hc_carryfree_index(i, j)
+
+
+def hc_carryfree_workspace_bytes(n: int, dtype: int) -> int:
+    return lib().hc_carryfree_workspace_bytes(n, dtype)
+
+
+def hc_carryfree_convolve(x: int, y: int, n: int, z: int, dtype: int, ws: int, ws_bytes: int, stream: int) -> int:
+    return lib().hc_carryfree_convolve(x, y, n, z, dtype, ws, ws_bytes, stream)
+
+
+def hc_difference_workspace_bytes(D: int, dtype: int, batch: int = 1) -> int:
+    return lib().hc_difference_workspace_bytes(D, dtype, batch)
+
+
+def hc_difference_batch(x: int, y: int, z: int, D: int, dtype: int, batch: int, ws: int, ws_bytes: int,
+                        stream: int) -> int:
+    return lib().hc_difference_batch(x, y, z, D, dtype, batch, ws, ws_bytes, stream)
 
 
 def hc_profile_enable(on: bool) -> int:

@@ -124,12 +124,6 @@ static hipEvent_t pooled_event()
     return e;
 }
 
-template <typename T>
-const char* tname()
-{
-    return sizeof(T) == 4 ? "f32" : (std::is_same<T, double>::value ? "f64" : "i64");
-}
-
 LaunchScope::LaunchScope(hipStream_t s, double bytes, const char* fmt, ...) : stream_(s), on_(false), idx_(0)
 {
     if (!g_prof_on || g_quiet > 0) return;

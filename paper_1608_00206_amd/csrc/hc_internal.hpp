@@ -5,6 +5,7 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <type_traits>
 #include <vector>
 
 #include "hc_device.hpp"
@@ -62,6 +63,13 @@ class CaptureScope {
     CaptureScope(const CaptureScope&) = delete;
     CaptureScope& operator=(const CaptureScope&) = delete;
 };
+
+// Short element-type name for profiler labels.
+template <typename T>
+const char* tname()
+{
+    return sizeof(T) == 4 ? "f32" : (std::is_same<T, double>::value ? "f64" : "i64");
+}
 
 int fail(int code, const char* fmt, ...);
 int hip_fail(hipError_t e, const char* what);

@@ -146,3 +146,47 @@ def test_plan_validation():
     assert _abi.lib().hc_plan_workspace_bytes(None) == _abi.SIZE_MAX
     assert _abi.lib().hc_plan_destroy(None) == 0
     assert _abi.lib().hc_plan_execute(None, 0, 0, 0, 0, 0, None) == 1
+
+
+# ------------------------------------------------ applications (host side)
+
+def test_carryfree_dim_and_index():
+    assert [_abi.hc_carryfree_dim(n) for n in (1, 2, 3, 4, 5, 1000, 1 << 21)] == [0, 1, 2, 2, 3, 10, 21]
+    assert _abi.hc_carryfree_dim(0) == -1
+    assert _abi.hc_carryfree_dim((1 << 21) + 1) == -1
+    # the Discussion's example: bits (1,1,1) + (1,0,1) = digits (2,1,2)
+    assert _abi.hc_carryfree_index(7, 5) == 2 * 9 + 1 * 3 + 2
+    for i, j in [(0, 0), (1, 0), (3, 6), (1000, 77)]:
+        k, w, a, b = 0, 1, i, j
+        while a or b:
+            k += ((a & 1) + (b & 1)) * w
+            a, b, w = a >> 1, b >> 1, w * 3
+        assert _abi.hc_carryfree_index(i, j) == k
+
+
+def test_application_workspace_sizes():
+    f64 = _abi.HC_F64
+    # a power-of-two length needs only the convolution's workspace
+    assert _abi.hc_carryfree_workspace_bytes(1 << 12, f64) == _abi.hc_workspace_bytes(12, f64)
+    # otherwise two zero-padded copies come first
+    assert _abi.hc_carryfree_workspace_bytes(3000, f64) >= 2 * 4096 * 8 + _abi.hc_workspace_bytes(12, f64)
+    assert _abi.hc_carryfree_workspace_bytes(0, f64) == _abi.SIZE_MAX
+    assert _abi.hc_carryfree_workspace_bytes(5, 9) == _abi.SIZE_MAX
+    assert _abi.hc_difference_workspace_bytes(10, f64, 3) >= 3 * 1024 * 8 + _abi.hc_workspace_bytes(10, f64, 3)
+    assert _abi.hc_difference_workspace_bytes(-1, f64, 1) == _abi.SIZE_MAX
+
+
+def test_application_validation():
+    x, y, z = FAKE, FAKE + (1 << 22), FAKE + (1 << 26)
+    cf = _abi.hc_carryfree_convolve
+    assert cf(0, y, 100, z, 0, 0, 0, 0) == 1                   # null x
+    assert cf(x, y, 0, z, 0, 0, 0, 0) == 2                      # n = 0
+    assert cf(x, y, 100, z, 7, 0, 0, 0) == 3                    # dtype
+    assert cf(x + 4, y, 100, z, 0, FAKE + (1 << 30), 1 << 20, 0) == 5   # misaligned
+    assert cf(x, y, 100, z, 0, 0, 0, 0) == 6                    # padding needs a workspace
+    assert cf(x, y, 100, x + 64, 0, FAKE + (1 << 30), 1 << 20, 0) == 4  # z overlaps x
+    df = _abi.hc_difference_batch
+    assert df(x, y, z, 22, 0, 1, 0, 0, 0) == 2
+    assert df(x, y, z, 10, 0, 0, 0, 0, 0) == 1                   # batch 0
+    assert df(x, y, z, 10, 0, 1, 0, 0, 0) == 6                   # no workspace
+    assert df(x, y, y + 8, 10, 0, 1, FAKE + (1 << 30), 1 << 20, 0) == 4  # z overlaps y
