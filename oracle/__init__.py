@@ -82,6 +82,10 @@ def _load():
     lib.hco_correlation_at_f64.restype = None
     lib.hco_bound_f64.argtypes = [P, P, P, I]
     lib.hco_bound_f64.restype = I
+    lib.hco_maxconv_at_f64.argtypes = [P, P, I, P, I64, P]
+    lib.hco_maxconv_at_f64.restype = None
+    lib.hco_pnorm_at_f64.argtypes = [P, P, I, ctypes.c_double, P, I64, P]
+    lib.hco_pnorm_at_f64.restype = None
     lib.hco_bound_at_f64.argtypes = [P, P, I, P, I64, P]
     lib.hco_bound_at_f64.restype = I
     lib.hco_adjoint_bound_f64.argtypes = [P, P, P, P, P, I]
@@ -228,6 +232,32 @@ def correlation_at(x, y, w, idx):
     _load().hco_correlation_at_f64(_ptr(x), _ptr(y), _ptr(w), D, _ptr(idx), idx.size,
                                    _ptr(gx), _ptr(gy))
     return gx, gy
+
+
+def _at_f64(fn, x, y, ks, *extra):
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    x, y, D, _ = _pair(x, y)
+    ks = np.ascontiguousarray(ks, dtype=np.uint64).reshape(-1)
+    if ks.size and int(ks.max()) >= 3 ** D:
+        raise ValueError("output index out of range")
+    out = np.empty(ks.size, dtype=np.float64)
+    if extra:
+        fn(_ptr(x), _ptr(y), D, *extra, _ptr(ks), ks.size, _ptr(out))
+    else:
+        fn(_ptr(x), _ptr(y), D, _ptr(ks), ks.size, _ptr(out))
+    return out
+
+
+def maxconv_at(x, y, ks) -> np.ndarray:
+    """Max-convolution max x[i]*y[j] over the pairs of each output index."""
+    return _at_f64(_load().hco_maxconv_at_f64, x, y, ks)
+
+
+def pnorm_at(x, y, p, ks) -> np.ndarray:
+    """p-norm estimate (sum (x[i] y[j])^p)^(1/p) of the max-convolution at
+    the given output indices (nonnegative inputs)."""
+    return _at_f64(_load().hco_pnorm_at_f64, x, y, ks, ctypes.c_double(float(p)))
 
 
 def bound(x, y) -> np.ndarray:

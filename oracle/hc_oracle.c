@@ -18,7 +18,8 @@
  *   hco_adjoint_*    transposed maps (gradient of sum(w * z))
  *   hco_carryfree_naive_*   carry-free 1-D convolution by its definition
  *   hco_difference_naive_*  distribution of X - Y by its definition
- * plus fp64/long double helpers for pins: the ternary index map, the direct
+ * plus fp64/long double helpers for pins: the max-convolution and its p-norm
+ * estimate at single indices, the ternary index map, the direct
  * per-element definition sum, the direct correlation gradient and the
  * rounding-error bound.
  */
@@ -149,6 +150,81 @@ void hco_direct_at_i64(const uint64_t* x, const uint64_t* y, int D,
             acc += x[i] * y[j];
         }
         out[r] = acc;
+    }
+}
+
+/* Pairs (i, j) that meet at output k: digit 0 fixes bits (0,0), digit 2
+ * fixes (1,1), digit 1 admits (0,1) and (1,0).  Fills base_i, base_j and the
+ * bit positions of the 1 digits; returns their number. */
+static int hco_pairs_of(uint64_t k, int D, uint64_t* base_i, uint64_t* base_j, int* ones_bits)
+{
+    int n_ones = 0;
+    *base_i = *base_j = 0;
+    for (int d = 0; d < D; ++d) {
+        const uint64_t digit = k % 3;
+        k /= 3;
+        if (digit == 2) { *base_i |= (uint64_t)1 << d; *base_j |= (uint64_t)1 << d; }
+        else if (digit == 1) ones_bits[n_ones++] = d;
+    }
+    return n_ones;
+}
+
+/* Max-convolution on the semiring (x, max) (Discussion), by its definition
+ * at single output indices: z_max[k] = max over the pairs of k of x[i]*y[j]. */
+void hco_maxconv_at_f64(const double* x, const double* y, int D, const uint64_t* ks, int64_t n, double* out)
+{
+    for (int64_t r = 0; r < n; ++r) {
+        uint64_t bi, bj;
+        int ones[64];
+        const int s = hco_pairs_of(ks[r], D, &bi, &bj, ones);
+        double m = -INFINITY;
+        for (uint64_t q = 0; q < ((uint64_t)1 << s); ++q) {
+            uint64_t i = bi, j = bj;
+            for (int b = 0; b < s; ++b) {
+                if ((q >> b) & 1u) i |= (uint64_t)1 << ones[b];
+                else j |= (uint64_t)1 << ones[b];
+            }
+            const double v = x[i] * y[j];
+            if (v > m) m = v;
+        }
+        out[r] = m;
+    }
+}
+
+/* p-norm estimate of the max-convolution (Discussion: p-norm rings):
+ *   z_p[k] = (sum over the pairs of k of (x[i] y[j])^p)^(1/p)
+ * for nonnegative inputs.  Evaluated stably by factoring out the output's
+ * largest term t_max (the max-convolution itself):
+ *   z_p[k] = t_max (sum (t / t_max)^p)^(1/p),
+ * with long double powers and a compensated sum, so no power under- or
+ * overflows.  It brackets the maximum: z_max <= z_p <= 2^(s/p) z_max, with
+ * s the number of 1 digits of k. */
+void hco_pnorm_at_f64(const double* x, const double* y, int D, double p, const uint64_t* ks, int64_t n,
+                      double* out)
+{
+    for (int64_t r = 0; r < n; ++r) {
+        uint64_t bi, bj;
+        int ones[64];
+        const int s = hco_pairs_of(ks[r], D, &bi, &bj, ones);
+        const uint64_t n_terms = (uint64_t)1 << s;
+        long double tmax = 0.0L;
+        for (int pass = 0; pass < 2; ++pass) {
+            hco_acc acc = {0.0L, 0.0L};
+            for (uint64_t q = 0; q < n_terms; ++q) {
+                uint64_t i = bi, j = bj;
+                for (int b = 0; b < s; ++b) {
+                    if ((q >> b) & 1u) i |= (uint64_t)1 << ones[b];
+                    else j |= (uint64_t)1 << ones[b];
+                }
+                const long double t = (long double)x[i] * (long double)y[j];
+                if (pass == 0) {
+                    if (t > tmax) tmax = t;
+                } else if (tmax > 0.0L) {
+                    hco_acc_add(&acc, powl(t / tmax, (long double)p));
+                }
+            }
+            if (pass == 1) out[r] = (double)(tmax > 0.0L ? tmax * powl(acc.s + acc.c, 1.0L / (long double)p) : 0.0L);
+        }
     }
 }
 

@@ -112,3 +112,60 @@ def test_difference_deltas_symmetry_and_mass(D):
     # X - Y and Y - X are mirror images: digit d <-> 2 - d, i.e. k <-> 3^D - 1 - k
     assert np.array_equal(z, oracle.difference_naive(y, x)[::-1])
     assert z.sum() == x.sum() * y.sum()
+
+
+# ------------------------------------------ max-convolution and its p-norm
+
+def brute_maxconv(x, y, D):
+    """max over (i, j) of x[i] y[j] with output digits bit(i) + bit(j), by
+    enumerating every pair (independent of the oracle's index logic)."""
+    z = np.full(3 ** D, -np.inf)
+    for i in range(1 << D):
+        for j in range(1 << D):
+            k = 0
+            for a in range(D - 1, -1, -1):
+                k = 3 * k + ((i >> a) & 1) + ((j >> a) & 1)
+            z[k] = max(z[k], x[i] * y[j])
+    return z
+
+
+def ones_count(D):
+    return np.array([sum(d == 1 for d in pins.ternary_digits(k, D)) for k in range(3 ** D)])
+
+
+@pytest.mark.parametrize("D", [0, 1, 2, 4, 6])
+def test_maxconv_matches_brute_force(D):
+    g = np.random.default_rng([66, D])
+    x = g.random(1 << D)
+    y = g.random(1 << D)
+    ks = np.arange(3 ** D, dtype=np.uint64)
+    assert np.array_equal(oracle.maxconv_at(x, y, ks), brute_maxconv(x, y, D))
+
+
+@pytest.mark.parametrize("D", [1, 4, 7])
+def test_pnorm_brackets_the_maximum_and_converges(D):
+    g = np.random.default_rng([67, D])
+    x = g.random(1 << D)
+    y = g.random(1 << D)
+    ks = np.arange(3 ** D, dtype=np.uint64)
+    zmax = oracle.maxconv_at(x, y, ks)
+    s = ones_count(D)
+    # p = 1 is the ordinary convolution (definition sum)
+    assert np.allclose(oracle.pnorm_at(x, y, 1.0, ks), oracle.direct_at(x, y, ks), rtol=1e-15, atol=0)
+    for p in (2.0, 7.5, 64.0, 4096.0):
+        zp = oracle.pnorm_at(x, y, p, ks)
+        assert np.all(zp >= zmax * (1 - 1e-15))
+        assert np.all(zp <= zmax * 2.0 ** (s / p) * (1 + 1e-15))
+    # scaling an input scales the estimate
+    assert np.allclose(oracle.pnorm_at(3 * x, y, 9.0, ks), 3 * oracle.pnorm_at(x, y, 9.0, ks), rtol=1e-14)
+
+
+def test_pnorm_single_term_is_exact():
+    """With one nonzero pair per output the p-norm is that product for any p."""
+    x = np.array([0.0, 0.0, 0.0, 0.75])
+    y = np.array([0.0, 0.5, 0.0, 0.0])
+    ks = np.arange(9, dtype=np.uint64)
+    for p in (1.0, 3.0, 100.0):
+        z = oracle.pnorm_at(x, y, p, ks)
+        assert np.flatnonzero(z).tolist() == [oracle.tern(3) + oracle.tern(1)]
+        assert z.max() == 0.375
