@@ -11,14 +11,17 @@ HIP-event-timed duration on the launch stream, against the 8 TB/s HBM peak),
 and the CPU oracle timed on a bounded sample of the same workload.
 
 Workloads (inputs from hc_inputs, seeded and synthetic):
-  all       (default) d20 as the headline value, plus batched and backward
-            measured after it and reported under "secondary"
+  all       (default) d20 as the headline value, plus batched, backward and
+            apps measured after it and reported under "secondary"
   d20       one pair, D=20, float64 masses (3^20 outputs)
   d16-f64   one pair, D=16, float64 masses
   d16-i64   one pair, D=16, int64 values in [0, 15]
   d10       one pair, D=10, float64 masses
   batched   4096 pairs, D uniform in {6..14}, masses, float64 and float32
   backward  64 pairs at D=16 float64, forward + backward of sum(w * z)
+  apps      carry-free convolution of two length-10^6 vectors, the
+            distribution of X - Y and the p-norm max-convolution (p = 32),
+            both at D=20 (float64)
 """
 from __future__ import annotations
 
@@ -263,6 +266,52 @@ def run_single(args, torch, hc, D, dtype_name):
     return res
 
 
+def run_apps(args, torch, hc, steps=None, warmup=None):
+    """The applications built on the forward path (Discussion): carry-free
+    convolution of two length-10^6 float64 vectors (D = 20 after padding) and
+    the distribution of X - Y for two D = 20 float64 distributions."""
+    import numpy as np
+
+    import hc_inputs
+    dev = torch.device("cuda:0")
+    steps = steps or args.steps
+    warmup = args.warmup if warmup is None else warmup
+    out = {}
+    n = 1_000_000
+    g = hc_inputs.rng(hc_inputs.W_D20_F64, 0, 9)
+    x = torch.from_numpy(g.random(n)).to(dev)
+    y = torch.from_numpy(g.random(n)).to(dev)
+    D = hc.carryfree_dim(n)
+    z = torch.empty(3 ** D, dtype=torch.float64, device=dev)
+    ws = torch.empty(hc._abi.hc_carryfree_workspace_bytes(n, hc._abi.HC_F64), dtype=torch.uint8, device=dev)
+    ms, _, st = time_steps(lambda: hc.carryfree_convolve(x, y, out=z, workspace=ws), steps, warmup, torch)
+    log(f"carry-free n={n}: {ms:.3f} ms/step")
+    out["carryfree_n1e6_f64"] = {"n": n, "D": D, "ms_per_step": round(ms, 4),
+                                 "output_elems_per_s": round(3 ** D / (ms / 1e3), 1),
+                                 "kernels": kernel_table(st, steps)}
+    del x, y, ws
+    D = 20
+    xa, ya = hc_inputs.pair_masses(D, hc_inputs.W_D20_F64)
+    x = torch.from_numpy(xa).to(dev)
+    y = torch.from_numpy(ya).to(dev)
+    ws = torch.empty(hc._abi.hc_difference_workspace_bytes(D, hc._abi.HC_F64, 1), dtype=torch.uint8, device=dev)
+    ms, _, st = time_steps(lambda: hc.difference(x, y, out=z, workspace=ws), steps, warmup, torch)
+    log(f"difference D={D}: {ms:.3f} ms/step")
+    out["difference_D20_f64"] = {"D": D, "ms_per_step": round(ms, 4),
+                                 "output_elems_per_s": round(3 ** D / (ms / 1e3), 1),
+                                 "kernels": kernel_table(st, steps)}
+    del ws
+    ws = torch.empty(hc._abi.hc_maxconv_workspace_bytes(D, hc._abi.HC_F64, 1), dtype=torch.uint8, device=dev)
+    ms, _, st = time_steps(lambda: hc.maxconv_pnorm(x, y, 32.0, out=z, workspace=ws), steps, warmup, torch)
+    log(f"p-norm max-convolution D={D} p=32: {ms:.3f} ms/step")
+    out["maxconv_p32_D20_f64"] = {"D": D, "p": 32.0, "ms_per_step": round(ms, 4),
+                                  "output_elems_per_s": round(3 ** D / (ms / 1e3), 1),
+                                  "kernels": kernel_table(st, steps)}
+    del x, y, z, ws
+    torch.cuda.empty_cache()
+    return out
+
+
 def run_batched(args, torch, hc, steps=None, warmup=None):
     """4096 pairs with D drawn uniformly from {6, ..., 14}: one graph launch of
     the batched plan per step, in float64 and float32; compared with a loop
@@ -379,7 +428,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="all",
-                    choices=["all", "d20", "d16-f64", "d16-i64", "d10", "batched", "backward"])
+                    choices=["all", "d20", "d16-f64", "d16-i64", "d10", "batched", "backward", "apps"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain copy kernel of known size before the workload (for counter passes)")
@@ -405,6 +454,8 @@ def main():
         copy_calibration(torch)
     if args.workload == "backward":
         res = run_backward(args, torch, hc)
+    elif args.workload == "apps":
+        res = {"metric": METRIC, "applications": run_apps(args, torch, hc)}
     elif args.workload == "batched":
         b = run_batched(args, torch, hc)
         res = {"metric": METRIC, "value": b["f64"]["pairs_per_s"], "unit": "pairs/s", "n_gpus": 1,
@@ -422,7 +473,8 @@ def main():
             torch.cuda.empty_cache()
             sec_steps = max(2, min(args.steps, 5))
             res["secondary"] = {"batched_4096_pairs": run_batched(args, torch, hc, sec_steps, 1),
-                                "backward_64xD16_f64": run_backward(args, torch, hc, sec_steps, 1)}
+                                "backward_64xD16_f64": run_backward(args, torch, hc, sec_steps, 1),
+                                "applications": run_apps(args, torch, hc, sec_steps, 1)}
     print(json.dumps(res), flush=True)
 
 

@@ -269,6 +269,33 @@ int hc_difference_batch(const void* x, const void* y, void* z, int D, int dtype,
                         size_t workspace_bytes, hipStream_t stream);
 
 /*
+ * p-norm estimate of the max-convolution on the semiring (x, max)
+ * (Discussion: p-norm rings): for nonnegative inputs and each batch item,
+ *   z[k] = (sum over the pairs (i, j) of output k of (x[i] y[j])^p)^(1/p)
+ * which lies between max_{pairs} x[i] y[j] and 2^(s/p) times it (s = number
+ * of digits of k equal to 1).  Computed as mx my (conv((x/mx)^p, (y/my)^p))^(1/p)
+ * with mx, my each input's maximum and the convolution of this library;
+ * negative entries count as 0.  Limits: powers below the smallest float
+ * vanish (outputs below about mx my * 2^(-1074/p) for float64 read 0), and the
+ * inverse map's cancellation leaves a relative error of about
+ * (4D+2) u B/(p z'), B the method's rounding bound of the powered inputs, so
+ * very large p lose the small outputs (see the design notes for measurements).
+ * With HC_MAXCONV_ROUND every estimate is rounded to the nearest integer,
+ * which gives the exact max-convolution of small integers where both the
+ * 2^(s/p) factor and the rounding error stay below one half.
+ *   x, y        device, batch x 2^D elements (read only), float64 or float32
+ *   z           device, batch x 3^D elements (written)
+ *   p           finite, >= 1 (p = 1 is the ordinary convolution)
+ *   workspace   hc_maxconv_workspace_bytes(D, dtype, batch) bytes
+ * Errors: as hc_convolve_batch; HC_ERR_UNSUPPORTED for int64,
+ * HC_ERR_INVALID_ARG for p or unknown flags.
+ */
+#define HC_MAXCONV_ROUND 1u
+size_t hc_maxconv_workspace_bytes(int D, int dtype, int batch);  /* (size_t)-1 if invalid */
+int hc_maxconv_pnorm_batch(const void* x, const void* y, void* z, int D, int dtype, int batch, double p,
+                           unsigned flags, void* workspace, size_t workspace_bytes, hipStream_t stream);
+
+/*
  * Kernel profiler (measurement support; not part of the method).
  * While enabled, every kernel launch of the calling process is bracketed by
  * a pair of HIP events recorded on the launch stream, and tagged with the

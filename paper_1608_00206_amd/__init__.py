@@ -26,7 +26,8 @@ from ._abi import HCError
 
 __all__ = ["convolve", "convolve_batch", "convolve_backward", "HypercubeConv", "HCError", "BatchedPlan",
            "workspace_bytes", "backward_workspace_bytes", "dim_of", "DTYPES",
-           "carryfree_convolve", "carryfree_index", "carryfree_dim", "difference", "difference_batch"]
+           "carryfree_convolve", "carryfree_index", "carryfree_dim", "difference", "difference_batch",
+           "maxconv_pnorm", "maxconv_pnorm_batch"]
 
 DTYPES = {torch.float64: _abi.HC_F64, torch.float32: _abi.HC_F32, torch.int64: _abi.HC_I64}
 
@@ -239,6 +240,46 @@ def difference(x: torch.Tensor, y: torch.Tensor, out: torch.Tensor | None = None
     D = dim_of(x.numel())
     flat = out.view(1, 3 ** D) if out is not None else None
     return difference_batch(x.view(1, -1), y.view(1, -1), out=flat, workspace=workspace).view(3 ** D)
+
+
+def maxconv_pnorm_batch(x: torch.Tensor, y: torch.Tensor, p: float, round: bool = False,
+                        out: torch.Tensor | None = None, workspace: torch.Tensor | None = None) -> torch.Tensor:
+    """p-norm estimate of the max-convolution max x[i] y[j] of nonnegative
+    (B, 2^D) float64/float32 inputs: (sum (x[i] y[j])^p)^(1/p) per output;
+    round=True rounds the estimates to integers.  Returns (B, 3^D)."""
+    if x.dim() != 2 or x.shape != y.shape:
+        raise ValueError("x and y must both have shape (B, 2^D)")
+    if x.dtype != y.dtype:
+        raise TypeError("x and y must have the same dtype")
+    _check_device(x, y)
+    B, n = x.shape
+    D = dim_of(n)
+    code = _dtype_code(x)
+    x = x.contiguous()
+    y = y.contiguous()
+    if out is None:
+        out = torch.empty((B, 3 ** D), dtype=x.dtype, device=x.device)
+    elif out.shape != (B, 3 ** D) or out.dtype != x.dtype or not out.is_contiguous() or out.device != x.device:
+        raise ValueError("out must be a contiguous (B, 3^D) tensor of the input dtype")
+    nbytes = _abi.hc_maxconv_workspace_bytes(D, code, B)
+    if nbytes == _abi.SIZE_MAX:
+        raise TypeError("the p-norm max-convolution supports float64 and float32")
+    ws = _workspace(nbytes, x.device, workspace)
+    _abi.check(_abi.hc_maxconv_pnorm_batch(x.data_ptr(), y.data_ptr(), out.data_ptr(), D, code, B, float(p),
+                                           _abi.HC_MAXCONV_ROUND if round else 0, ws.data_ptr(), nbytes,
+                                           _stream(x.device)))
+    return out
+
+
+def maxconv_pnorm(x: torch.Tensor, y: torch.Tensor, p: float, round: bool = False,
+                  out: torch.Tensor | None = None, workspace: torch.Tensor | None = None) -> torch.Tensor:
+    """Single-pair form of maxconv_pnorm_batch: (2^D,) inputs, (3^D,) output."""
+    if x.dim() != 1 or x.shape != y.shape:
+        raise ValueError("x and y must be 1-D tensors of the same length 2^D")
+    D = dim_of(x.numel())
+    flat = out.view(1, 3 ** D) if out is not None else None
+    return maxconv_pnorm_batch(x.view(1, -1), y.view(1, -1), p, round=round, out=flat,
+                               workspace=workspace).view(3 ** D)
 
 
 class HypercubeConv(torch.autograd.Function):

@@ -72,6 +72,8 @@ SIGNATURES = {
     "hc_carryfree_convolve": ([_P, _P, _U64, _P, _I, _P, _SZ, _P], _I),
     "hc_difference_workspace_bytes": ([_I, _I, _I], _SZ),
     "hc_difference_batch": ([_P, _P, _P, _I, _I, _I, _P, _SZ, _P], _I),
+    "hc_maxconv_workspace_bytes": ([_I, _I, _I], _SZ),
+    "hc_maxconv_pnorm_batch": ([_P, _P, _P, _I, _I, _I, ctypes.c_double, ctypes.c_uint, _P, _SZ, _P], _I),
     "hc_profile_enable": ([_I], _I),
     "hc_profile_collect": ([ctypes.POINTER(KernelStat), _I, ctypes.POINTER(_I)], _I),
 }
@@ -170,6 +172,18 @@ def hc_difference_workspace_bytes(D: int, dtype: int, batch: int = 1) -> int:
 def hc_difference_batch(x: int, y: int, z: int, D: int, dtype: int, batch: int, ws: int, ws_bytes: int,
                         stream: int) -> int:
     return lib().hc_difference_batch(x, y, z, D, dtype, batch, ws, ws_bytes, stream)
+
+
+HC_MAXCONV_ROUND = 1
+
+
+def hc_maxconv_workspace_bytes(D: int, dtype: int, batch: int = 1) -> int:
+    return lib().hc_maxconv_workspace_bytes(D, dtype, batch)
+
+
+def hc_maxconv_pnorm_batch(x: int, y: int, z: int, D: int, dtype: int, batch: int, p: float, flags: int, ws: int,
+                           ws_bytes: int, stream: int) -> int:
+    return lib().hc_maxconv_pnorm_batch(x, y, z, D, dtype, batch, p, flags, ws, ws_bytes, stream)
 
 
 def hc_profile_enable(on: bool) -> int:

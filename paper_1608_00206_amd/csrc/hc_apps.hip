@@ -10,8 +10,17 @@
 //     every axis maps bit b to 1 - b, so the convolution of x with the
 //     reflected y puts x[i] y[j] at digits bit(i) + 1 - bit(j) = (X - Y) + 1.
 //
-// Both reuse hc_convolve_batch unchanged; the only new device work is one
-// padding or reflecting copy into the caller's workspace.
+//   p-norm estimate of the max-convolution (Discussion: p-norm rings): for
+//     nonnegative x, y,  z[k] ~ max over the pairs of k of x[i] y[j], as
+//     (sum (x[i] y[j])^p)^(1/p) = mx my (conv((x/mx)^p, (y/my)^p)[k])^(1/p),
+//     mx, my the inputs' maxima; the convolution is exact up to rounding, so
+//     larger p stay usable than with an FFT, until cancellation in the
+//     inverse map (relative error ~ (4D+2) u B/z' of the powered result)
+//     dominates.  Optionally rounded to integers.
+//
+// All three reuse hc_convolve_batch unchanged; the new device work is a
+// padding, reflecting or powering copy into the caller's workspace (and the
+// root of the p-norm in place on z).
 #include "hc.h"
 #include "hc_internal.hpp"
 
@@ -59,6 +68,102 @@ static void launch_reflect(const T* src, T* dst, uint64_t n2, int batch, int cus
     LaunchScope scope(s, 2.0 * batch * n2 * sizeof(T), "reflect<%s>", tname<T>());
     dim3 grid(copy_grid(n2, cus), batch, 1);
     k_reflect<T><<<grid, APP_NT, 0, s>>>(src, dst, n2);
+}
+
+// Per item and operand, the largest entry (negative entries count as 0):
+// scales[op * batch + b].  One workgroup per (item, operand).
+constexpr int MAX_NT = 1024;
+template <typename T>
+__global__ __launch_bounds__(MAX_NT) void k_maxscale(const T* __restrict__ x, const T* __restrict__ y,
+                                                     uint64_t n2, T* __restrict__ scales)
+{
+    __shared__ T red[MAX_NT];
+    const T* src = (blockIdx.y ? y : x) + (uint64_t)blockIdx.x * n2;
+    T m = T(0);
+    for (uint64_t i = threadIdx.x; i < n2; i += MAX_NT) {
+        const T v = src[i];
+        m = v > m ? v : m;
+    }
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int h = MAX_NT / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) red[threadIdx.x] = red[threadIdx.x + h] > red[threadIdx.x] ? red[threadIdx.x + h]
+                                                                                              : red[threadIdx.x];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) scales[(uint64_t)blockIdx.y * gridDim.x + blockIdx.x] = red[0];
+}
+
+template <typename T>
+__device__ __forceinline__ T pow_t(T a, T b)
+{
+    if constexpr (sizeof(T) == 4) return powf(a, b);
+    else return pow(a, b);
+}
+
+// xp[b][i] = (x[b][i] / mx_b)^p, yp likewise (0 where the entry or the scale
+// is not positive).  blockIdx.y = item, blockIdx.z = operand.
+template <typename T>
+__global__ __launch_bounds__(APP_NT) void k_power(const T* __restrict__ x, const T* __restrict__ y,
+                                                  T* __restrict__ xp, T* __restrict__ yp,
+                                                  const T* __restrict__ scales, uint64_t n2, T p)
+{
+    const int op = blockIdx.z;
+    const uint64_t off = (uint64_t)blockIdx.y * n2;
+    const T* src = (op ? y : x) + off;
+    T* dst = (op ? yp : xp) + off;
+    const T m = scales[(uint64_t)op * gridDim.y + blockIdx.y];
+    for (uint64_t i = (uint64_t)blockIdx.x * APP_NT + threadIdx.x; i < n2; i += (uint64_t)gridDim.x * APP_NT) {
+        const T v = src[i];
+        dst[i] = (v > T(0) && m > T(0)) ? pow_t<T>(v / m, p) : T(0);
+    }
+}
+
+// z[b][k] = mx_b my_b max(z[b][k], 0)^(1/p), optionally rounded to an integer
+template <typename T>
+__global__ __launch_bounds__(APP_NT) void k_root(T* __restrict__ z, const T* __restrict__ scales, uint64_t n3,
+                                                 T inv_p, int round)
+{
+    const uint64_t off = (uint64_t)blockIdx.y * n3;
+    const T s = scales[blockIdx.y] * scales[gridDim.y + blockIdx.y];
+    for (uint64_t k = (uint64_t)blockIdx.x * APP_NT + threadIdx.x; k < n3; k += (uint64_t)gridDim.x * APP_NT) {
+        const T v = z[off + k];
+        T r = v > T(0) ? s * pow_t<T>(v, inv_p) : T(0);
+        if (round) r = rint(r);
+        z[off + k] = r;
+    }
+}
+
+template <typename T>
+static int maxconv_t(const T* x, const T* y, T* z, int D, int batch, double p, bool round, char* ws,
+                     size_t ws_bytes, int cus, hipStream_t s)
+{
+    const uint64_t n2 = 1ull << D, n3 = pow3u(D);
+    T* scales = reinterpret_cast<T*>(ws);
+    const size_t sc_b = round256(2 * (size_t)batch * sizeof(T));
+    const size_t op_b = round256((size_t)batch * n2 * sizeof(T));
+    T* xp = reinterpret_cast<T*>(ws + sc_b);
+    T* yp = reinterpret_cast<T*>(ws + sc_b + op_b);
+    {
+        LaunchScope scope(s, 2.0 * batch * n2 * sizeof(T), "maxscale<%s>", tname<T>());
+        k_maxscale<T><<<dim3(batch, 2, 1), MAX_NT, 0, s>>>(x, y, n2, scales);
+    }
+    {
+        LaunchScope scope(s, 4.0 * batch * n2 * sizeof(T), "power<%s>", tname<T>());
+        k_power<T><<<dim3(copy_grid(n2, cus), batch, 2), APP_NT, 0, s>>>(x, y, xp, yp, scales, n2, (T)p);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "max-convolution launch");
+    const int rc = hc_convolve_batch(xp, yp, z, D, sizeof(T) == 4 ? HC_F32 : HC_F64, batch, ws + sc_b + 2 * op_b,
+                                     ws_bytes - sc_b - 2 * op_b, s);
+    if (rc != HC_OK) return rc;
+    {
+        LaunchScope scope(s, 2.0 * batch * n3 * sizeof(T), "root<%s>", tname<T>());
+        k_root<T><<<dim3(copy_grid(n3, cus), batch, 1), APP_NT, 0, s>>>(z, scales, n3, (T)(1.0 / p), round ? 1 : 0);
+    }
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "max-convolution launch");
+    return HC_OK;
 }
 
 static int carryfree_dim(uint64_t n)
@@ -184,6 +289,50 @@ int hc_difference_batch(const void* x, const void* y, void* z, int D, int dtype,
     if (e != hipSuccess) return hip_fail(e, "reflect launch");
     const size_t r_b = round256(in_b);
     return hc_convolve_batch(x, ws, z, D, dtype, batch, ws + r_b, workspace_bytes - r_b, stream);
+}
+
+size_t hc_maxconv_workspace_bytes(int D, int dtype, int batch)
+{
+    if (D < 0 || D > HC_MAX_D || (dtype != HC_F64 && dtype != HC_F32) || batch < 1) return (size_t)-1;
+    const size_t es = dtype_size(dtype);
+    return round256(2 * (size_t)batch * es) + 2 * round256((size_t)batch * ((size_t)1 << D) * es) +
+           hc_workspace_bytes(D, dtype, batch);
+}
+
+int hc_maxconv_pnorm_batch(const void* x, const void* y, void* z, int D, int dtype, int batch, double p,
+                           unsigned flags, void* workspace, size_t workspace_bytes, hipStream_t stream)
+{
+    if (!x || !y || !z) return fail(HC_ERR_INVALID_ARG, "x, y and z must be non-null");
+    if (D < 0 || D > HC_MAX_D) return fail(HC_ERR_D_RANGE, "D=%d outside [0, %d]", D, HC_MAX_D);
+    if (dtype != HC_F64 && dtype != HC_F32)
+        return fail(HC_ERR_UNSUPPORTED, "the p-norm max-convolution supports float64 and float32 only");
+    if (batch < 1 || batch > 65535) return fail(HC_ERR_INVALID_ARG, "batch=%d outside [1, 65535]", batch);
+    if (!(p >= 1.0) || !(p <= 1e300)) return fail(HC_ERR_INVALID_ARG, "p must be a finite number >= 1");
+    if (flags & ~HC_MAXCONV_ROUND) return fail(HC_ERR_INVALID_ARG, "unknown flags 0x%x", flags);
+    const size_t es = dtype_size(dtype);
+    if (misaligned(x, es) || misaligned(y, es) || misaligned(z, es) || misaligned(workspace, 16))
+        return fail(HC_ERR_MISALIGNED, "data must be aligned to the element size, the workspace to 16 bytes");
+    const size_t need = hc_maxconv_workspace_bytes(D, dtype, batch);
+    if (!workspace || workspace_bytes < need)
+        return fail(HC_ERR_WORKSPACE, "workspace of %zu bytes required, %zu given", need,
+                    workspace ? workspace_bytes : (size_t)0);
+    const uint64_t n2 = 1ull << D;
+    const size_t in_b = (size_t)batch * n2 * es, out_b = (size_t)batch * pow3u(D) * es;
+    if (ranges_overlap(workspace, need, x, in_b) || ranges_overlap(workspace, need, y, in_b))
+        return fail(HC_ERR_ALIAS, "workspace overlaps x or y");
+    if (ranges_overlap(z, out_b, x, in_b) || ranges_overlap(z, out_b, y, in_b) ||
+        ranges_overlap(z, out_b, workspace, need))
+        return fail(HC_ERR_ALIAS, "z overlaps x, y or the workspace");
+    int cus = 0;
+    int rc = device_cus(&cus);
+    if (rc != HC_OK) return rc;
+    const bool round = (flags & HC_MAXCONV_ROUND) != 0;
+    char* ws = static_cast<char*>(workspace);
+    if (dtype == HC_F64)
+        return maxconv_t<double>((const double*)x, (const double*)y, (double*)z, D, batch, p, round, ws,
+                                 workspace_bytes, cus, stream);
+    return maxconv_t<float>((const float*)x, (const float*)y, (float*)z, D, batch, p, round, ws, workspace_bytes,
+                            cus, stream);
 }
 
 }  // extern "C"

@@ -190,3 +190,19 @@ def test_application_validation():
     assert df(x, y, z, 10, 0, 0, 0, 0, 0) == 1                   # batch 0
     assert df(x, y, z, 10, 0, 1, 0, 0, 0) == 6                   # no workspace
     assert df(x, y, y + 8, 10, 0, 1, FAKE + (1 << 30), 1 << 20, 0) == 4  # z overlaps y
+
+
+def test_maxconv_validation():
+    x, y, z, ws = FAKE, FAKE + (1 << 22), FAKE + (1 << 26), FAKE + (1 << 30)
+    f = _abi.hc_maxconv_pnorm_batch
+    big = 1 << 24
+    assert _abi.hc_maxconv_workspace_bytes(10, _abi.HC_I64, 1) == _abi.SIZE_MAX
+    need = _abi.hc_maxconv_workspace_bytes(10, _abi.HC_F64, 2)
+    assert need >= 2 * 2 * 1024 * 8 + _abi.hc_workspace_bytes(10, _abi.HC_F64, 2)
+    assert f(x, y, z, 10, _abi.HC_I64, 1, 2.0, 0, ws, big, 0) == 3      # int64 unsupported
+    assert f(x, y, z, 10, 0, 1, 0.5, 0, ws, big, 0) == 1                 # p < 1
+    assert f(x, y, z, 10, 0, 1, float("nan"), 0, ws, big, 0) == 1
+    assert f(x, y, z, 10, 0, 1, float("inf"), 0, ws, big, 0) == 1
+    assert f(x, y, z, 10, 0, 1, 2.0, 4, ws, big, 0) == 1                 # unknown flag
+    assert f(x, y, z, 10, 0, 1, 2.0, 0, 0, 0, 0) == 6                    # workspace
+    assert f(x, y, x + 8, 10, 0, 1, 2.0, 0, ws, big, 0) == 4             # z overlaps x

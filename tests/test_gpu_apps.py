@@ -142,3 +142,111 @@ def test_application_errors():
     rc = hc._abi.hc_carryfree_convolve(x.data_ptr(), x.data_ptr(), 10, z.data_ptr(), hc._abi.HC_F64,
                                        ws.data_ptr(), nbytes - 8, 0)
     assert rc == 6
+
+
+# ------------------------------------------------- p-norm max-convolution
+
+def pnorm_tolerance(x, y, p, D, z_ref, dtype):
+    """Per-output tolerance of the GPU estimate against the exact p-norm.
+
+    With zp = (z_ref / (mx my))^p the exact powered convolution, the GPU's
+    powered convolution is within E of it: each powered input carries a
+    relative error of at most (p+2)u (the scaled input's rounding amplified
+    by p, plus the power's own), the method adds at most (4D+2) u B' (B' its
+    rounding bound), and products or sums below the dtype's normal range
+    round to its subnormal spacing (at most (4D+2) 2^D such operations per
+    output).  The root then moves the estimate by at most
+    mx my ((zp + E)^(1/p) - zp^(1/p)) up and mx my (zp^(1/p) - (zp - E)^(1/p))
+    down, plus a few u for the root and the rescaling.  Where cancellation
+    makes E much larger than zp the estimate may exceed the p-norm several
+    times over: the method's limit for large p."""
+    u = oracle.unit_roundoff(dtype)
+    tiny = float(np.finfo(dtype).smallest_subnormal)
+    mx, my = float(x.max()), float(y.max())
+    xp = (x.astype(np.float64) / mx) ** p
+    yp = (y.astype(np.float64) / my) ** p
+    Bp = oracle.bound(xp, yp)
+    zp = (z_ref / (mx * my)) ** p
+    E = (2 * p + 5) * u * zp + (4 * D + 2) * u * Bp + (4 * D + 2) * (1 << D) * tiny
+    r = zp ** (1.0 / p)
+    above = (zp + E) ** (1.0 / p) - r
+    below = r - np.maximum(zp - E, 0.0) ** (1.0 / p)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        eps = E / zp
+    return mx * my * np.maximum(above, below) + 8 * u * z_ref, eps
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("p", [1.0, 2.0, 7.5, 32.0])
+@pytest.mark.parametrize("D", [0, 1, 3, 6, 9])
+def test_maxconv_pnorm_matches_oracle(dtype, p, D):
+    x, y = hc_inputs.random_pair(D, dtype, 5)
+    z = hc.maxconv_pnorm(on_gpu(x), on_gpu(y), p)
+    torch.cuda.synchronize(DEV)
+    z = z.cpu().numpy().astype(np.float64)
+    ks = np.arange(3 ** D, dtype=np.uint64)
+    if np.dtype(dtype) == np.float64:
+        # the p-norm itself (no power of these inputs leaves float64's range)
+        ref = oracle.pnorm_at(x, y, p, ks)
+    else:
+        # float32 powers of small scaled inputs underflow (0.2^32 * 0.2^32 is
+        # below the smallest float32): the reference is the exact convolution
+        # of the same float32 powers, rooted
+        mx, my = float(x.max()), float(y.max())
+        xp = np.power(x / np.float32(mx), np.float32(p)).astype(np.float64)
+        yp = np.power(y / np.float32(my), np.float32(p)).astype(np.float64)
+        ref = mx * my * np.power(np.maximum(oracle.direct_at(xp, yp, ks), 0.0), 1.0 / p)
+    tol, _ = pnorm_tolerance(x, y, p, D, ref, dtype)
+    assert np.all(np.abs(z - ref) <= tol), f"max excess {np.max(np.abs(z - ref) - tol)}"
+
+
+def test_maxconv_p1_is_the_convolution():
+    """p = 1 is the ordinary convolution of the scaled inputs; the device
+    power may move an input by an ulp, which the method's conditioning
+    (its rounding bound B) carries to the outputs."""
+    D = 8
+    x, y = hc_inputs.random_pair(D, np.float64, 6)
+    z1 = hc.maxconv_pnorm(on_gpu(x), on_gpu(y), 1.0).cpu().numpy()
+    mx, my = x.max(), y.max()
+    zc = oracle.canonical(x / mx, y / my) * mx * my
+    u = 2.0 ** -53
+    tol = (4 * D + 6) * u * oracle.bound(x / mx, y / my) * mx * my + 4 * u * np.abs(zc)
+    assert np.all(np.abs(z1 - zc) <= tol)
+
+
+@pytest.mark.parametrize("R,D,p", [(1, 10, 32.0), (3, 8, 32.0), (15, 6, 64.0)])
+def test_maxconv_rounding_exact_where_certified(R, D, p):
+    """Bounded integers: rounding the estimate gives the exact max-convolution
+    at every output where the 2^(s/p) bias and the certified rounding error
+    stay below one half; the certified share is reported."""
+    g = np.random.default_rng([hc_inputs.SEED, 89, R, D])
+    x = g.integers(0, R + 1, 1 << D).astype(np.float64)
+    y = g.integers(0, R + 1, 1 << D).astype(np.float64)
+    z = hc.maxconv_pnorm(on_gpu(x), on_gpu(y), p, round=True).cpu().numpy()
+    ks = np.arange(3 ** D, dtype=np.uint64)
+    zmax = oracle.maxconv_at(x, y, ks)
+    ref = oracle.pnorm_at(x, y, p, ks)
+    tol, eps = pnorm_tolerance(x, y, p, D, ref, np.float64)
+    s = np.array([sum(d == 1 for d in pins.ternary_digits(int(k), D)) for k in ks])
+    # the estimate is within tol of the p-norm, which is within
+    # (2^(s/p) - 1) zmax above the maximum (for zmax = 0, tol alone)
+    certified = (2.0 ** (s / p) - 1) * zmax + tol < 0.5
+    assert np.array_equal(z[certified], zmax[certified])
+    share = certified.mean()
+    print(f"R={R} D={D} p={p}: {share:.1%} of outputs certified, "
+          f"{np.mean(z == zmax):.1%} exact overall")
+    assert share > (0.95 if R == 1 else 0.1)
+
+
+def test_maxconv_batch_and_errors():
+    D, B = 7, 4
+    xs = np.stack([hc_inputs.random_pair(D, np.float64, 10 + b)[0] for b in range(B)])
+    ys = np.stack([hc_inputs.random_pair(D, np.float64, 10 + b)[1] for b in range(B)])
+    Z = hc.maxconv_pnorm_batch(on_gpu(xs), on_gpu(ys), 16.0).cpu().numpy()
+    for b in range(B):
+        zb = hc.maxconv_pnorm(on_gpu(xs[b]), on_gpu(ys[b]), 16.0).cpu().numpy()
+        assert np.array_equal(Z[b], zb)
+    with pytest.raises(TypeError):
+        hc.maxconv_pnorm(on_gpu(np.ones(4, dtype=np.int64)), on_gpu(np.ones(4, dtype=np.int64)), 2.0)
+    with pytest.raises(hc.HCError):
+        hc.maxconv_pnorm(on_gpu(np.ones(4)), on_gpu(np.ones(4)), 0.5)
