@@ -113,12 +113,16 @@ def profiler_name(demangled: str):
     return None
 
 
-def write_traffic(fetch_csv: str, write_csv: str) -> None:
-    """Turns two rocprofv3 counter passes (FETCH_SIZE, then WRITE_SIZE, both
-    over `--workload ... --copy-calibration`) into the traffic table: KiB per
-    dispatch averaged per kernel, and the factors that map each counter onto
-    the calibration copy's known bytes."""
+def write_traffic(csvs) -> None:
+    """Turns rocprofv3 counter passes into the traffic table.  `csvs` lists
+    pairs (FETCH_SIZE pass, WRITE_SIZE pass), each pair taken over one
+    `--workload ... --copy-calibration` run: KiB per dispatch averaged per
+    kernel, and the factors that map each counter onto the calibration
+    copy's known bytes (averaged over the runs)."""
     import csv
+
+    if len(csvs) % 2:
+        raise SystemExit("--write-traffic takes FETCH_CSV WRITE_CSV pairs")
 
     def per_kernel(path, counter):
         acc, cal = {}, []
@@ -135,14 +139,25 @@ def write_traffic(fetch_csv: str, write_csv: str) -> None:
                     acc.setdefault(pn, []).append(val)
         if len(cal) != 1:
             raise SystemExit(f"{path}: expected one calibration copy dispatch, found {len(cal)}")
-        return {k: sum(v) / len(v) for k, v in acc.items()}, cal[0]
+        return acc, cal[0]
 
-    fetch, fcal = per_kernel(fetch_csv, "FETCH_SIZE")
-    write, wcal = per_kernel(write_csv, "WRITE_SIZE")
+    fetch, write, fcals, wcals = {}, {}, [], []
+    for i in range(0, len(csvs), 2):
+        f, fc = per_kernel(csvs[i], "FETCH_SIZE")
+        w, wc = per_kernel(csvs[i + 1], "WRITE_SIZE")
+        fcals.append(fc)
+        wcals.append(wc)
+        for k, v in f.items():
+            fetch.setdefault(k, []).extend(v)
+        for k, v in w.items():
+            write.setdefault(k, []).extend(v)
+    fcal = sum(fcals) / len(fcals)
+    wcal = sum(wcals) / len(wcals)
     out = {"kernel_source_sha": kernel_source_hash(), "unit": "KiB per dispatch",
            "copy_calibration_bytes": COPY_CAL_BYTES, "copy_fetch_kib": fcal, "copy_write_kib": wcal,
            "fetch_scale": COPY_CAL_BYTES / (fcal * 1024.0), "write_scale": COPY_CAL_BYTES / (wcal * 1024.0),
-           "kernels": {k: {"fetch_kib": fetch[k], "write_kib": write[k]} for k in sorted(fetch) if k in write}}
+           "kernels": {k: {"fetch_kib": sum(fetch[k]) / len(fetch[k]), "write_kib": sum(write[k]) / len(write[k])}
+                       for k in sorted(fetch) if k in write}}
     with open(TRAFFIC_FILE, "w") as f:
         json.dump(out, f, indent=1)
         f.write("\n")
@@ -432,11 +447,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain copy kernel of known size before the workload (for counter passes)")
-    ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
-                    help="write profiles/traffic.json from two rocprofv3 counter CSVs and exit")
+    ap.add_argument("--write-traffic", nargs="+", metavar="CSV",
+                    help="write profiles/traffic.json from rocprofv3 counter CSVs (FETCH_SIZE WRITE_SIZE pairs) "
+                         "and exit")
     args = ap.parse_args()
     if args.write_traffic:
-        write_traffic(*args.write_traffic)
+        write_traffic(args.write_traffic)
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
