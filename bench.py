@@ -56,10 +56,10 @@ def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def measured_traffic(kernel: str, launches_per_step: float):
-    """HBM bytes per launch of `kernel` from committed rocprofv3 counter runs
-    (FETCH_SIZE and WRITE_SIZE, scaled by a copy-kernel calibration), or None
-    when none were taken on the current kernel source."""
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of `kernel` in `workload` from committed rocprofv3
+    counter runs (FETCH_SIZE and WRITE_SIZE, scaled by a copy-kernel
+    calibration), or None when none were taken on the current kernel source."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
@@ -67,7 +67,7 @@ def measured_traffic(kernel: str, launches_per_step: float):
         return None
     if t.get("kernel_source_sha") != kernel_source_hash():
         return None
-    k = t.get("kernels", {}).get(kernel)
+    k = t.get("workloads", {}).get(workload, {}).get(kernel)
     if not k:
         return None
     return (k["fetch_kib"] * t["fetch_scale"] + k["write_kib"] * t["write_scale"]) * 1024.0
@@ -113,16 +113,16 @@ def profiler_name(demangled: str):
     return None
 
 
-def write_traffic(csvs) -> None:
-    """Turns rocprofv3 counter passes into the traffic table.  `csvs` lists
-    pairs (FETCH_SIZE pass, WRITE_SIZE pass), each pair taken over one
-    `--workload ... --copy-calibration` run: KiB per dispatch averaged per
-    kernel, and the factors that map each counter onto the calibration
-    copy's known bytes (averaged over the runs)."""
+def write_traffic(args) -> None:
+    """Turns rocprofv3 counter passes into the traffic table.  `args` lists
+    triples WORKLOAD FETCH_CSV WRITE_CSV, each pair of passes taken over one
+    `--workload WORKLOAD --copy-calibration` run: KiB per dispatch averaged
+    per kernel and workload, and the factors that map each counter onto the
+    calibration copy's known bytes (averaged over the runs)."""
     import csv
 
-    if len(csvs) % 2:
-        raise SystemExit("--write-traffic takes FETCH_CSV WRITE_CSV pairs")
+    if len(args) % 3:
+        raise SystemExit("--write-traffic takes WORKLOAD FETCH_CSV WRITE_CSV triples")
 
     def per_kernel(path, counter):
         acc, cal = {}, []
@@ -141,23 +141,21 @@ def write_traffic(csvs) -> None:
             raise SystemExit(f"{path}: expected one calibration copy dispatch, found {len(cal)}")
         return acc, cal[0]
 
-    fetch, write, fcals, wcals = {}, {}, [], []
-    for i in range(0, len(csvs), 2):
-        f, fc = per_kernel(csvs[i], "FETCH_SIZE")
-        w, wc = per_kernel(csvs[i + 1], "WRITE_SIZE")
+    workloads, fcals, wcals = {}, [], []
+    for i in range(0, len(args), 3):
+        wl, fpath, wpath = args[i:i + 3]
+        f, fc = per_kernel(fpath, "FETCH_SIZE")
+        w, wc = per_kernel(wpath, "WRITE_SIZE")
         fcals.append(fc)
         wcals.append(wc)
-        for k, v in f.items():
-            fetch.setdefault(k, []).extend(v)
-        for k, v in w.items():
-            write.setdefault(k, []).extend(v)
+        workloads[wl] = {k: {"fetch_kib": sum(f[k]) / len(f[k]), "write_kib": sum(w[k]) / len(w[k])}
+                         for k in sorted(f) if k in w}
     fcal = sum(fcals) / len(fcals)
     wcal = sum(wcals) / len(wcals)
     out = {"kernel_source_sha": kernel_source_hash(), "unit": "KiB per dispatch",
            "copy_calibration_bytes": COPY_CAL_BYTES, "copy_fetch_kib": fcal, "copy_write_kib": wcal,
            "fetch_scale": COPY_CAL_BYTES / (fcal * 1024.0), "write_scale": COPY_CAL_BYTES / (wcal * 1024.0),
-           "kernels": {k: {"fetch_kib": sum(fetch[k]) / len(fetch[k]), "write_kib": sum(write[k]) / len(write[k])}
-                       for k in sorted(fetch) if k in write}}
+           "workloads": workloads}
     with open(TRAFFIC_FILE, "w") as f:
         json.dump(out, f, indent=1)
         f.write("\n")
@@ -187,13 +185,13 @@ def time_steps(fn, steps: int, warmup: int, torch):
     return ev0.elapsed_time(ev1) / steps, wall, stats
 
 
-def roofline(stats, steps: int):
+def roofline(stats, steps: int, workload: str):
     dom = max(stats, key=lambda s: s[2])
     name, launches, total_ms, alg_bytes = dom
     avg_s = total_ms / launches / 1e3
     per_launch = alg_bytes / launches
     achieved = per_launch / avg_s / 1e9
-    traffic = measured_traffic(name, launches / steps)
+    traffic = measured_traffic(name, workload)
     return {"bound": "hbm", "kernel": name, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": None if traffic is None else round(traffic),
@@ -270,7 +268,7 @@ def run_single(args, torch, hc, D, dtype_name):
         "scaling": "weak", "vs_baseline": None, "dtype": dtype_name, "data": "synthetic",
         "config": {"workload": desc, "D": D, "outputs_per_step": n_out, "global_batch": 1,
                    "parallelism": "single GPU"},
-        "roofline": roofline(stats, args.steps),
+        "roofline": roofline(stats, args.steps, args.workload if args.workload != "all" else "d20"),
         "compulsory_hbm_frac": round((n_out + 2 * (1 << D)) * z.element_size() / (ms / 1e3) / 1e9
                                      / HBM_PEAK_GBS, 4),
         "kernels": kernel_table(stats, args.steps),
@@ -432,7 +430,7 @@ def run_backward(args, torch, hc, steps=None, warmup=None):
         "config": {"workload": f"{B} pairs D={D} float64 masses, loss sum(w*z), w iid N(0,1) per pair",
                    "D": D, "global_batch": B, "parallelism": "single GPU"},
         "fwd_ms": round(fwd_ms, 4), "bwd_ms": round(bwd_ms, 4), "fwd_bwd_ms": round(fwd_ms + bwd_ms, 4),
-        "roofline": roofline(bstats, steps),
+        "roofline": roofline(bstats, steps, "backward"),
         "kernels": kernel_table(fstats, steps) + kernel_table(bstats, steps),
     }
 
@@ -447,9 +445,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain copy kernel of known size before the workload (for counter passes)")
-    ap.add_argument("--write-traffic", nargs="+", metavar="CSV",
-                    help="write profiles/traffic.json from rocprofv3 counter CSVs (FETCH_SIZE WRITE_SIZE pairs) "
-                         "and exit")
+    ap.add_argument("--write-traffic", nargs="+", metavar="ARG",
+                    help="write profiles/traffic.json from rocprofv3 counter CSVs given as WORKLOAD FETCH_CSV "
+                         "WRITE_CSV triples, and exit")
     args = ap.parse_args()
     if args.write_traffic:
         write_traffic(args.write_traffic)
