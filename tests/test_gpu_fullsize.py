@@ -199,3 +199,29 @@ def test_backward_64_pairs_d16():
         lm = torch.dot(hc.convolve(xm, Y[p]), w).item()
         fd = (lp - lm) / (2 * h)
         assert abs(fd - gx[p][i]) <= 1e-6 * scale, (i, fd, gx[p][i])
+
+
+def test_d21_f64_maximum_size_sampled():
+    """D = 21, the largest D accepted (84 GB of float64 output): sampled
+    outputs within the certified bound of the definition, the total mass and
+    the all-zero-digits corner."""
+    D = 21
+    n3 = 3 ** D
+    g = np.random.default_rng([hc_inputs.SEED, 80, D])
+    x = g.random(1 << D)
+    x /= x.sum()
+    y = g.random(1 << D)
+    y /= y.sum()
+    say("D=21 float64: GPU")
+    z = hc.convolve(on_gpu(x), on_gpu(y))
+    torch.cuda.synchronize(DEV)
+    assert z.numel() == n3
+    ks = sample_indices(D, 256, 3)
+    z_at = z[torch.from_numpy(ks.astype(np.int64)).to(DEV)].cpu().numpy()
+    r = check_against_definition(x, y, z_at, ks, D)
+    assert z_at[0] == x[0] * y[0] and z_at[-1] == x[-1] * y[-1]
+    total = float(z.sum().item())
+    assert abs(total - float(x.sum()) * float(y.sum())) < 1e-12
+    say(f"D=21 float64: max |err|/(u B) over {ks.size} sampled outputs = {r:.2f}; sum z - 1 = {total - 1:.2e}")
+    del z
+    torch.cuda.empty_cache()
