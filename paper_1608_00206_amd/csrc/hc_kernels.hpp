@@ -8,7 +8,8 @@
 //   outer forward   F on axes 0..p-1           x: 2^D -> 3^p x 2^K   (fwd_column)
 //   fused inner     per outer index o: F on axes p..D-1, product, G on axes
 //                   D-1..p, one contiguous 3^K row of z            (fused_tile)
-//   outer inverse   G on axes p-1..0 in groups, in place on z      (inv_tile)
+//   outer inverse   G on axes p-1..0 in groups, in place on z
+//                                                     (inv_tile, inv_tile_r4)
 // which applies every map in exactly the canonical axis order, so the result
 // is bitwise independent of K, of the grouping and of the tiling.
 //
@@ -17,7 +18,8 @@
 // fwd_adj_column (F^T on outer axes, descending).
 //
 // Each step is a device function working on one tile or column, called by
-// the single-problem kernels below and by the batched persistent kernel.
+// the kernels below; a batch item (a uniform batch or one pair of a batched
+// plan) is selected by blockIdx.y through per-item offset maps (BMap).
 #pragma once
 
 #include "hc_device.hpp"
@@ -264,11 +266,12 @@ struct PassCfg {
     static constexpr int LDS = mW == 0 ? 0 : (THIRDS ? 3 : 2) * tW * S_GA * 64;  // elements
 };
 
-// One tile of an inverse pass.  `wave` must be wave-uniform; waves with
-// wave >= PassCfg::WAVES take part in the barriers only.  S holds
-// PassCfg::LDS elements when mW > 0.  EXACT: the workgroup has exactly
-// PassCfg::WAVES waves and, when mW > 0, every wave is known to be active.
-template <typename T, int mR, int mW, int CW, bool ADJ, bool IN_PLACE, bool EXACT = false>
+// One tile of an inverse pass, run by a workgroup of exactly PassCfg::WAVES
+// waves; `wave` must be wave-uniform.  S holds PassCfg::LDS elements when
+// mW > 0.  With a wave part every wave is active (the tile's first column
+// j * 64 is below L); without one, a wave whose 64 columns all lie past L
+// skips its work.
+template <typename T, int mR, int mW, int CW, bool ADJ, bool IN_PLACE>
 __device__ __forceinline__ void inv_tile(const T* src, T* dst, uint64_t L, uint32_t hi, uint32_t j, int wave, T* S)
 {
     using P = PassCfg<mR, mW, CW>;
@@ -278,8 +281,7 @@ __device__ __forceinline__ void inv_tile(const T* src, T* dst, uint64_t L, uint3
     const int cg = wave / tW;
     const int gW1 = wave - cg * tW;
     const uint64_t lo_w = (uint64_t)j * P::COLS + (uint64_t)cg * 64;  // this wave's first column
-    // with a wave part the tile's first column lo_w = j * 64 is always < L
-    const bool active = (EXACT && mW > 0) ? true : (wave < P::WAVES && lo_w < L);
+    const bool active = mW > 0 || lo_w < L;
     const uint32_t col_off = (uint32_t)lane * (uint32_t)sizeof(T);
     const uint32_t seg_bytes = (uint32_t)((L - lo_w < 64 ? L - lo_w : 64) * sizeof(T));  // when active
     const uint64_t row_bytes = L * sizeof(T);
@@ -533,7 +535,7 @@ __global__ __launch_bounds__(64 * pow3c(mW) * CW) void k_inv_pass(const T* src, 
             const uint32_t hi = t / tiles_per_hi;
             const uint32_t j = t - hi * tiles_per_hi;
             if constexpr (mW > 0) lds_barrier();  // the previous tile's phase-2 reads are done
-            inv_tile<T, mR, mW, CW, ADJ, IN_PLACE, true>(src, dst, L, hi, j, wave, S);
+            inv_tile<T, mR, mW, CW, ADJ, IN_PLACE>(src, dst, L, hi, j, wave, S);
         }
     }
 }
