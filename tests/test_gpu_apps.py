@@ -157,7 +157,8 @@ def pnorm_tolerance(x, y, p, D, z_ref, dtype):
     round to its subnormal spacing (at most (4D+2) 2^D such operations per
     output).  The root then moves the estimate by at most
     mx my ((zp + E)^(1/p) - zp^(1/p)) up and mx my (zp^(1/p) - (zp - E)^(1/p))
-    down, plus a few u for the root and the rescaling.  Where cancellation
+    down, plus the root's own error (computed as exp(log(z')/p): a few u
+    times 1 + |ln z'|/p) and the rescaling.  Where cancellation
     makes E much larger than zp the estimate may exceed the p-norm several
     times over: the method's limit for large p."""
     u = oracle.unit_roundoff(dtype)
@@ -173,7 +174,9 @@ def pnorm_tolerance(x, y, p, D, z_ref, dtype):
     below = r - np.maximum(zp - E, 0.0) ** (1.0 / p)
     with np.errstate(divide="ignore", invalid="ignore"):
         eps = E / zp
-    return mx * my * np.maximum(above, below) + 8 * u * z_ref, eps
+    with np.errstate(divide="ignore"):
+        lnz = np.where(zp > 0, np.abs(np.log(np.where(zp > 0, zp, 1.0))), 0.0)
+    return mx * my * np.maximum(above, below) + (8 + 4 * lnz / p) * u * z_ref, eps
 
 
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
