@@ -316,7 +316,8 @@ int hc_profile_enable(int on);
 /*
  * Wait for every recorded event, aggregate by kernel name into `out`
  * (at most `capacity` entries, *count receives the number written) and
- * clear the record.  Errors: HC_ERR_INVALID_ARG (null count or out with
+ * clear the record.  Call it while no other thread is launching work through
+ * this library.  Errors: HC_ERR_INVALID_ARG (null count or out with
  * capacity > 0), HC_ERR_HIP.
  */
 int hc_profile_collect(hc_kernel_stat* out, int capacity, int* count);

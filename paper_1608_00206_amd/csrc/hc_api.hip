@@ -5,6 +5,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
@@ -104,7 +105,7 @@ struct ProfRec {
     hipEvent_t a, b;
 };
 static std::mutex g_prof_mu;
-static bool g_prof_on = false;
+static std::atomic<bool> g_prof_on{false};
 static thread_local int g_quiet = 0;  // > 0 inside a CaptureScope
 
 CaptureScope::CaptureScope() { ++g_quiet; }
@@ -137,7 +138,11 @@ LaunchScope::LaunchScope(hipStream_t s, double bytes, const char* fmt, ...) : st
     r.bytes = bytes;
     r.a = pooled_event();
     r.b = pooled_event();
-    if (!r.a || !r.b) return;
+    if (!r.a || !r.b) {
+        if (r.a) g_event_pool.push_back(r.a);
+        if (r.b) g_event_pool.push_back(r.b);
+        return;
+    }
     if (hipEventRecord(r.a, s) != hipSuccess) return;
     g_prof.push_back(r);
     idx_ = g_prof.size() - 1;
