@@ -206,3 +206,15 @@ def test_maxconv_validation():
     assert f(x, y, z, 10, 0, 1, 2.0, 4, ws, big, 0) == 1                 # unknown flag
     assert f(x, y, z, 10, 0, 1, 2.0, 0, 0, 0, 0) == 6                    # workspace
     assert f(x, y, x + 8, 10, 0, 1, 2.0, 0, ws, big, 0) == 4             # z overlaps x
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    """Without libhc.so the binding raises instead of computing anything
+    another way (there is no CPU fallback)."""
+    monkeypatch.setattr(_abi, "_lib", None)
+    monkeypatch.setattr(_abi, "LIB_PATH", str(tmp_path / "libhc.so"))
+    with pytest.raises(ImportError, match="missing"):
+        _abi.hc_abi_version()
+    import paper_1608_00206_amd as hc
+    with pytest.raises(ImportError):
+        hc.workspace_bytes(10, __import__("torch").float64)
