@@ -280,6 +280,9 @@ int hc_difference_batch(const void* x, const void* y, void* z, int D, int dtype,
  * inverse map's cancellation leaves a relative error of about
  * (4D+2) u B/(p z'), B the method's rounding bound of the powered inputs, so
  * very large p lose the small outputs (see the design notes for measurements).
+ * The root itself is within 2 ulps of exact for integer p in [2, 1024]
+ * (float64 polishing of a float seed, for both dtypes) and within a few ulps
+ * times 1 + |ln z'|/p for other p (computed as exp(log(z')/p)).
  * With HC_MAXCONV_ROUND every estimate is rounded to the nearest integer,
  * which gives the exact max-convolution of small integers where both the
  * 2^(s/p) factor and the rounding error stay below one half.

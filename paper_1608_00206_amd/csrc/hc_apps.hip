@@ -21,6 +21,8 @@
 // All three reuse hc_convolve_batch unchanged; the new device work is a
 // padding, reflecting or powering copy into the caller's workspace (and the
 // root of the p-norm in place on z).
+#include <cmath>
+
 #include "hc.h"
 #include "hc_internal.hpp"
 
@@ -133,19 +135,63 @@ __device__ __forceinline__ T log_t(T a)
     else return log(a);
 }
 
-// z[b][k] = mx_b my_b max(z[b][k], 0)^(1/p), optionally rounded to an
-// integer.  The root is exp(log(v) / p): its relative error, a few ulps
-// times (1 + |ln v| / p), is far below the estimate's own 2^(s/p) bias, and
-// it costs a fraction of a general power over 3^D outputs (p = 1 skips it).
-template <typename T>
+// Integer p up to this bound take the polished root below; other p take
+// exp(log(v) / p).
+constexpr int ROOT_INT_MAX = 1024;
+
+// Coefficients of (1 + eps)^(1/p) = 1 + c1 eps + c2 eps^2 + c3 eps^3 + c4 eps^4 + ...
+struct RootCoef {
+    double c[4];
+    float inv_pf;  // 1/p rounded to float, for the seed
+};
+
+// v^(1/p) for finite v > 0 and integer 2 <= p <= ROOT_INT_MAX, in float64.
+// With v = m 2^e (m in [1/2, 1)) and e = n p + rem (|rem| <= p/2 + 1),
+// v^(1/p) = 2^n V^(1/p) for V = m 2^rem, which stays far inside the normal
+// range.  A float seed a ~ V^(1/p) (hardware log2 and exp2, relative error
+// ~1e-7) is polished with one step of the binomial series: A = a^p by binary
+// powering (relative error below (p - 1) u, worth under u after the 1/p
+// below), eps = V / A - 1 (V - A is exact, |eps| < 1e-3), and
+// V^(1/p) = a (1 + eps)^(1/p), the series cut after eps^4.  The result is
+// within 2 u of the exact root, with a margin of 10x on the seed's error.
+__device__ __forceinline__ double root_int(double v, int p, const RootCoef& rc)
+{
+    int e;
+    const double m = frexp(v, &e);
+    const int n = (int)rintf((float)e * rc.inv_pf);
+    const int rem = e - n * p;
+    const float t = ((float)rem + __builtin_amdgcn_logf((float)m)) * rc.inv_pf;
+    const double a = (double)__builtin_amdgcn_exp2f(t);
+    double A = 1.0, b = a;
+    for (int k = p;;) {
+        if (k & 1) A *= b;
+        k >>= 1;
+        if (!k) break;
+        b *= b;
+    }
+    const double V = ldexp(m, rem);
+    double q = __builtin_amdgcn_rcp(A);
+    q = fma(q, fma(-A, q, 1.0), q);
+    const double eps = (V - A) * q;
+    const double P = eps * (rc.c[0] + eps * (rc.c[1] + eps * (rc.c[2] + eps * rc.c[3])));
+    return ldexp(fma(a, P, a), n);
+}
+
+// How k_root takes the root: p = 1 needs none; integer p in
+// [2, ROOT_INT_MAX] take root_int (in float64 for both types); other p take
+// exp(log(v) / p), whose relative error is a few ulps times
+// 1 + |ln v| / p.  Either error is far below the estimate's own 2^(s/p) bias.
+enum RootMode { ROOT_NONE = 0, ROOT_INT = 1, ROOT_EXPLOG = 2 };
+
+// z[b][k] = mx_b my_b max(z[b][k], 0)^(1/p), optionally rounded to an integer.
+template <typename T, int MODE>
 __global__ __launch_bounds__(APP_NT) void k_root(T* __restrict__ z, const T* __restrict__ scales, uint64_t n3,
-                                                 T inv_p, int round)
+                                                 T inv_p, int ip, RootCoef rc, int round)
 {
     const uint64_t off = (uint64_t)blockIdx.y * n3;
     const T s = scales[blockIdx.y] * scales[gridDim.y + blockIdx.y];
-    const bool identity = inv_p == T(1);
     // four independent elements per thread and step keep loads in flight
-    // while the transcendental work of the previous ones runs
+    // while the arithmetic of the previous ones runs
     constexpr int U = 4;
     const uint64_t stride = (uint64_t)gridDim.x * APP_NT;
     for (uint64_t k0 = (uint64_t)blockIdx.x * APP_NT + threadIdx.x; k0 < n3; k0 += U * stride) {
@@ -159,7 +205,13 @@ __global__ __launch_bounds__(APP_NT) void k_root(T* __restrict__ z, const T* __r
         for (int q = 0; q < U; ++q) {
             const uint64_t k = k0 + q * stride;
             T r = T(0);
-            if (v[q] > T(0)) r = s * (identity ? v[q] : exp_t<T>(log_t<T>(v[q]) * inv_p));
+            if (v[q] > T(0)) {
+                T w;
+                if constexpr (MODE == ROOT_NONE) w = v[q];
+                else if constexpr (MODE == ROOT_INT) w = (T)root_int((double)v[q], ip, rc);
+                else w = exp_t<T>(log_t<T>(v[q]) * inv_p);
+                r = s * w;
+            }
             if (round) r = rint(r);
             if (k < n3) z[off + k] = r;
         }
@@ -191,7 +243,20 @@ static int maxconv_t(const T* x, const T* y, T* z, int D, int batch, double p, b
     if (rc != HC_OK) return rc;
     {
         LaunchScope scope(s, 2.0 * batch * n3 * sizeof(T), "root<%s>", tname<T>());
-        k_root<T><<<dim3(copy_grid(n3, cus), batch, 1), APP_NT, 0, s>>>(z, scales, n3, (T)(1.0 / p), round ? 1 : 0);
+        const int ip = (p == std::floor(p) && p >= 2 && p <= ROOT_INT_MAX) ? (int)p : 0;
+        RootCoef rc{};
+        const double c1 = 1.0 / p;
+        rc.c[0] = c1;
+        rc.c[1] = rc.c[0] * (c1 - 1) / 2;
+        rc.c[2] = rc.c[1] * (c1 - 2) / 3;
+        rc.c[3] = rc.c[2] * (c1 - 3) / 4;
+        rc.inv_pf = (float)c1;
+        const dim3 grid(copy_grid(n3, cus), batch, 1);
+        const T inv_p = (T)c1;
+        const int rnd = round ? 1 : 0;
+        if (p == 1) k_root<T, ROOT_NONE><<<grid, APP_NT, 0, s>>>(z, scales, n3, inv_p, ip, rc, rnd);
+        else if (ip) k_root<T, ROOT_INT><<<grid, APP_NT, 0, s>>>(z, scales, n3, inv_p, ip, rc, rnd);
+        else k_root<T, ROOT_EXPLOG><<<grid, APP_NT, 0, s>>>(z, scales, n3, inv_p, ip, rc, rnd);
     }
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "max-convolution launch");

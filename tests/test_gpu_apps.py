@@ -241,6 +241,42 @@ def test_maxconv_rounding_exact_where_certified(R, D, p):
     assert share > (0.95 if R == 1 else 0.1)
 
 
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("p", [2.0, 3.0, 32.0, 1000.0, 1024.0, 7.5, 1025.0])
+def test_maxconv_root_accuracy_over_wide_range(dtype, p):
+    """The root alone, over powered values spanning the dtype's normal range.
+    With x = [a, 1], y = [b, 1] and 0 < a, b < 1 the maxima are 1, output 0
+    is the single product a^p b^p and output 2 is 1, so the estimate at 0 is
+    (a^p b^p)^(1/p) = a b up to the two powers' and the product's rounding
+    (at most 3 u before the root, 3 u / p after it) and the root's own
+    error: at most 2 u for integer p up to 1024 (float64 polishing of a
+    float seed, float64 for both dtypes), a few u times 1 + |ln z'| / p for
+    other p (exp(log(z') / p))."""
+    g = np.random.default_rng([hc_inputs.SEED, 97, int(p * 2)])
+    B = 4096
+    fin = np.finfo(dtype)
+    lo = float(np.log2(fin.tiny)) + 2            # a^p b^p stays normal
+    ea = -g.random(B) * (-lo / p) / 2
+    eb = -g.random(B) * (-lo / p) / 2
+    a = np.exp2(ea).astype(dtype)
+    b = np.exp2(eb).astype(dtype)
+    one = np.ones(B, dtype=dtype)
+    X = np.stack([a, one], axis=1)
+    Y = np.stack([b, one], axis=1)
+    Z = hc.maxconv_pnorm_batch(on_gpu(X), on_gpu(Y), p).cpu().numpy()
+    assert np.all(Z[:, 2] == 1)
+    exact = a.astype(np.longdouble) * b.astype(np.longdouble)
+    rel = np.abs((Z[:, 0].astype(np.longdouble) - exact) / exact).astype(np.float64)
+    u = float(oracle.unit_roundoff(dtype))
+    zp = (exact ** p).astype(np.float64)
+    if p == int(p) and p <= 1024:
+        bound = (2 + 3 / p + 1) * u if dtype == np.float64 else (0.5 + 3 / p + 0.5) * u
+    else:
+        bound = (4 + 3 / p + 4 * np.abs(np.log(zp)) / p) * u
+    assert np.all(rel <= bound), f"worst {np.max(rel / u):.3f} u"
+    print(f"p={p} {np.dtype(dtype).name}: worst {np.max(rel) / u:.3f} u over z' down to {zp.min():.3g}")
+
+
 def test_maxconv_batch_and_errors():
     D, B = 7, 4
     xs = np.stack([hc_inputs.random_pair(D, np.float64, 10 + b)[0] for b in range(B)])
