@@ -72,7 +72,7 @@ typedef enum hc_status {
     HC_ERR_D_RANGE = 2,     /* D < 0 or D > HC_MAX_D */
     HC_ERR_UNSUPPORTED = 3, /* dtype not supported by this entry point */
     HC_ERR_ALIAS = 4,       /* an output overlaps an input or the workspace */
-    HC_ERR_MISALIGNED = 5,  /* a pointer is not aligned to its element size */
+    HC_ERR_MISALIGNED = 5,  /* data not aligned to its element size, a workspace not to 16 bytes */
     HC_ERR_WORKSPACE = 6,   /* workspace missing or smaller than required */
     HC_ERR_NO_DEVICE = 7,   /* no usable HIP device */
     HC_ERR_HIP = 8          /* a HIP runtime call failed */
@@ -205,7 +205,11 @@ int hc_plan_layout(const hc_plan* plan, uint64_t* x_offsets, uint64_t* z_offsets
 /*
  * Run the plan: z = x * y for every pair of the packed buffers.  x, y, z and
  * the workspace follow the conventions above (device, aligned, z disjoint
- * from the others).  Enqueued on `stream` as one graph launch.
+ * from the others).  Enqueued on `stream` as one graph launch.  A call with
+ * buffers other than the previous call's captures the graph again, so calls
+ * on one plan must not overlap in time from several host threads; launches
+ * of one plan on several streams share its workspace and must be ordered
+ * by the caller.
  * Errors: HC_ERR_INVALID_ARG, HC_ERR_ALIAS, HC_ERR_MISALIGNED,
  * HC_ERR_WORKSPACE, HC_ERR_HIP.
  */

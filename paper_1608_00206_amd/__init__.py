@@ -73,12 +73,20 @@ def backward_workspace_bytes(D: int, dtype: torch.dtype, batch: int = 1) -> int:
     return n
 
 
+def _launch(device: torch.device, fn, *args) -> None:
+    """Calls a libhc entry point with `device` current (the library works on
+    the current HIP device) and raises HCError on failure."""
+    with torch.cuda.device(device):
+        _abi.check(fn(*args))
+
+
 def _workspace(nbytes: int, device, workspace):
     if nbytes == 0:
         return None
     if workspace is not None:
-        if workspace.device != device or workspace.numel() * workspace.element_size() < nbytes:
-            raise ValueError(f"workspace needs {nbytes} bytes on {device}")
+        if (workspace.device != device or not workspace.is_contiguous()
+                or workspace.numel() * workspace.element_size() < nbytes):
+            raise ValueError(f"workspace must be a contiguous tensor of at least {nbytes} bytes on {device}")
         return workspace
     return torch.empty(nbytes, dtype=torch.uint8, device=device)
 
@@ -102,8 +110,8 @@ def convolve_batch(x: torch.Tensor, y: torch.Tensor, out: torch.Tensor | None = 
         raise ValueError("out must be a contiguous (B, 3^D) tensor of the input dtype")
     nbytes = workspace_bytes(D, x.dtype, B)
     ws = _workspace(nbytes, x.device, workspace)
-    _abi.check(_abi.hc_convolve_batch(x.data_ptr(), y.data_ptr(), out.data_ptr(), D, code, B,
-                                      ws.data_ptr() if ws is not None else 0, nbytes, _stream(x.device)))
+    _launch(x.device, _abi.hc_convolve_batch, x.data_ptr(), y.data_ptr(), out.data_ptr(), D, code, B,
+            ws.data_ptr() if ws is not None else 0, nbytes, _stream(x.device))
     return out
 
 
@@ -159,10 +167,9 @@ def convolve_backward(x: torch.Tensor, y: torch.Tensor, grad_z: torch.Tensor, ne
     gy = torch.empty_like(y) if need_y else None
     nbytes = backward_workspace_bytes(D, x.dtype, B)
     ws = _workspace(nbytes, x.device, workspace)
-    _abi.check(_abi.hc_convolve_backward_batch(
-        x.data_ptr(), y.data_ptr(), gz.data_ptr(), gz_stride,
-        gx.data_ptr() if gx is not None else 0, gy.data_ptr() if gy is not None else 0,
-        D, code, B, ws.data_ptr() if ws is not None else 0, nbytes, _stream(x.device)))
+    _launch(x.device, _abi.hc_convolve_backward_batch, x.data_ptr(), y.data_ptr(), gz.data_ptr(), gz_stride,
+            gx.data_ptr() if gx is not None else 0, gy.data_ptr() if gy is not None else 0,
+            D, code, B, ws.data_ptr() if ws is not None else 0, nbytes, _stream(x.device))
     return gx, gy
 
 
@@ -201,8 +208,8 @@ def carryfree_convolve(x: torch.Tensor, y: torch.Tensor, out: torch.Tensor | Non
         raise ValueError("out must be a contiguous tensor of 3^D elements of the input dtype")
     nbytes = _abi.hc_carryfree_workspace_bytes(n, code)
     ws = _workspace(nbytes, x.device, workspace)
-    _abi.check(_abi.hc_carryfree_convolve(x.data_ptr(), y.data_ptr(), n, out.data_ptr(), code,
-                                          ws.data_ptr() if ws is not None else 0, nbytes, _stream(x.device)))
+    _launch(x.device, _abi.hc_carryfree_convolve, x.data_ptr(), y.data_ptr(), n, out.data_ptr(), code,
+            ws.data_ptr() if ws is not None else 0, nbytes, _stream(x.device))
     return out
 
 
@@ -227,8 +234,8 @@ def difference_batch(x: torch.Tensor, y: torch.Tensor, out: torch.Tensor | None 
         raise ValueError("out must be a contiguous (B, 3^D) tensor of the input dtype")
     nbytes = _abi.hc_difference_workspace_bytes(D, code, B)
     ws = _workspace(nbytes, x.device, workspace)
-    _abi.check(_abi.hc_difference_batch(x.data_ptr(), y.data_ptr(), out.data_ptr(), D, code, B,
-                                        ws.data_ptr() if ws is not None else 0, nbytes, _stream(x.device)))
+    _launch(x.device, _abi.hc_difference_batch, x.data_ptr(), y.data_ptr(), out.data_ptr(), D, code, B,
+            ws.data_ptr() if ws is not None else 0, nbytes, _stream(x.device))
     return out
 
 
@@ -265,9 +272,9 @@ def maxconv_pnorm_batch(x: torch.Tensor, y: torch.Tensor, p: float, round: bool 
     if nbytes == _abi.SIZE_MAX:
         raise TypeError("the p-norm max-convolution supports float64 and float32")
     ws = _workspace(nbytes, x.device, workspace)
-    _abi.check(_abi.hc_maxconv_pnorm_batch(x.data_ptr(), y.data_ptr(), out.data_ptr(), D, code, B, float(p),
-                                           _abi.HC_MAXCONV_ROUND if round else 0, ws.data_ptr(), nbytes,
-                                           _stream(x.device)))
+    _launch(x.device, _abi.hc_maxconv_pnorm_batch, x.data_ptr(), y.data_ptr(), out.data_ptr(), D, code, B, float(p),
+            _abi.HC_MAXCONV_ROUND if round else 0, ws.data_ptr(), nbytes,
+            _stream(x.device))
     return out
 
 
@@ -352,12 +359,13 @@ class BatchedPlan:
         y = y.contiguous()
         if out is None:
             out = torch.empty(self.n_outputs, dtype=self.dtype, device=x.device)
-        elif out.numel() != self.n_outputs or out.dtype != self.dtype or not out.is_contiguous():
-            raise ValueError("out must be a contiguous tensor of n_outputs elements")
+        elif (out.numel() != self.n_outputs or out.dtype != self.dtype or not out.is_contiguous()
+              or out.device != x.device):
+            raise ValueError("out must be a contiguous tensor of n_outputs elements on the inputs' device")
         ws = _workspace(self.workspace_bytes, x.device, workspace)
-        _abi.check(_abi.hc_plan_execute(self._h, x.data_ptr(), y.data_ptr(), out.data_ptr(),
-                                        ws.data_ptr() if ws is not None else 0, self.workspace_bytes,
-                                        _stream(x.device)))
+        _launch(x.device, _abi.hc_plan_execute, self._h, x.data_ptr(), y.data_ptr(), out.data_ptr(),
+                ws.data_ptr() if ws is not None else 0, self.workspace_bytes,
+                _stream(x.device))
         return out
 
     def check(self) -> None:

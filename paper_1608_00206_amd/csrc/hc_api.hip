@@ -626,7 +626,7 @@ const char* hc_status_string(int status)
         case HC_ERR_D_RANGE: return "D out of range";
         case HC_ERR_UNSUPPORTED: return "unsupported dtype or configuration";
         case HC_ERR_ALIAS: return "output overlaps an input or the workspace";
-        case HC_ERR_MISALIGNED: return "pointer not 16-byte aligned";
+        case HC_ERR_MISALIGNED: return "pointer misaligned (data to its element size, workspaces to 16 bytes)";
         case HC_ERR_WORKSPACE: return "workspace missing or too small";
         case HC_ERR_NO_DEVICE: return "no HIP device";
         case HC_ERR_HIP: return "HIP runtime error";
