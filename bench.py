@@ -229,9 +229,33 @@ def cpu_baseline(x, y, z_gpu, D):
             equal = False
             break
     log(f"cpu baseline: {dt:.2f} s; GPU output bitwise equal: {equal}")
+    del out
+    # the same recursion on one thread, as the paper times its own method, on
+    # a smaller pair of the same kind
+    import hc_inputs
+    Ds = min(D, 17)
+    xs, ys = hc_inputs.pair_masses(Ds, hc_inputs.W_D20_F64)
+    t0 = time.perf_counter()
+    oracle.recursive(xs, ys, threads=1)
+    dt1 = time.perf_counter() - t0
+    log(f"cpu baseline, one thread, D={Ds}: {dt1:.2f} s")
     return {"value": round(3 ** D / dt, 1), "unit": "output elems/s", "cores": threads, "kind": "oracle",
             "sample": f"the whole workload (one D={D} pair), three-subproblem recursion",
-            "seconds": round(dt, 3), "gpu_output_bitwise_equal": equal}
+            "seconds": round(dt, 3), "gpu_output_bitwise_equal": equal, "cpu_model": cpu_model(),
+            "single_thread": {"value": round(3 ** Ds / dt1, 1), "unit": "output elems/s", "cores": 1,
+                              "sample": f"one D={Ds} float64 pair of the same distribution",
+                              "seconds": round(dt1, 3)}}
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def run_single(args, torch, hc, D, dtype_name):
