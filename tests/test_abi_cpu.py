@@ -218,3 +218,23 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     import paper_1608_00206_amd as hc
     with pytest.raises(ImportError):
         hc.workspace_bytes(10, __import__("torch").float64)
+
+
+def test_binding_rejects_bad_workspace_and_host_tensors():
+    """Host-side checks of the binding: a workspace must be one contiguous
+    block of enough bytes on the data's device, and host tensors never reach
+    the library."""
+    import torch
+
+    import paper_1608_00206_amd as hc
+    dev = torch.device("cpu")
+    good = torch.empty(64, dtype=torch.uint8)
+    assert hc._workspace(64, dev, good) is good
+    assert hc._workspace(0, dev, good) is None
+    with pytest.raises(ValueError):
+        hc._workspace(65, dev, good)
+    with pytest.raises(ValueError):
+        hc._workspace(16, dev, torch.empty(64, dtype=torch.uint8)[::2])
+    x = torch.ones(4, dtype=torch.float64)
+    with pytest.raises(ValueError, match="HIP device"):
+        hc.convolve(x, x)
