@@ -9,6 +9,9 @@ configuration the benchmark times (default plans, tuned batched plans).
   D=20 float64   every output (3^20 = 3.49e9) bitwise against the canonical
                  method (the recursion on 16 host threads), compared in
                  chunks; sampled outputs within the bound of the definition
+  D=17, 19 float64, D=20 float32, D=18 int64
+                 every output bitwise against the recursion (the other
+                 default plans at large D)
   batched        4096 pairs, D uniform in {6..14}, float64 and float32, tuned
                  plans: sampled pairs bitwise against the oracle, every pair
                  bitwise against single-pair calls
@@ -112,6 +115,36 @@ def test_d20_f64_every_output_bitwise():
     z_at = z_gpu[torch.from_numpy(ks.astype(np.int64)).to(DEV)].cpu().numpy()
     r = check_against_definition(x, y, z_at, ks, D)
     say(f"D=20 float64: max |err|/(u B) over {ks.size} sampled outputs = {r:.2f}")
+    del z_gpu, ref
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("D,dtype", [(17, np.float64), (19, np.float64), (20, np.float32), (18, np.int64)])
+def test_large_plans_every_output_bitwise(D, dtype):
+    """The default plans of the other large shapes (fused depth 9 and
+    different outer pass splits for float32, 5- and 6-axis pass pairs for
+    float64, int64 wrapping arithmetic), every output bitwise against the
+    recursion on 16 host threads."""
+    n3 = 3 ** D
+    if np.dtype(dtype) == np.int64:
+        x, y = hc_inputs.pair_ints(D, hc_inputs.W_D16)
+    else:
+        x, y = hc_inputs.pair_masses(D, hc_inputs.W_D20_F64)
+        x, y = x.astype(dtype), y.astype(dtype)
+    name = f"D={D} {np.dtype(dtype).name}"
+    say(f"{name}: GPU")
+    z_gpu = hc.convolve(on_gpu(x), on_gpu(y))
+    torch.cuda.synchronize(DEV)
+    ref = oracle.recursive(x, y, threads=16)
+    view = np.uint32 if np.dtype(dtype).itemsize == 4 else np.uint64
+    chunk = 1 << 28
+    mismatches = 0
+    for c0 in range(0, n3, chunk):
+        c1 = min(n3, c0 + chunk)
+        part = z_gpu[c0:c1].cpu().numpy()
+        mismatches += int(np.count_nonzero(part.view(view) != ref[c0:c1].view(view)))
+    say(f"{name}: {mismatches} of {n3} outputs differ")
+    assert mismatches == 0
     del z_gpu, ref
     torch.cuda.empty_cache()
 
