@@ -72,28 +72,56 @@ static void launch_reflect(const T* src, T* dst, uint64_t n2, int batch, int cus
     k_reflect<T><<<grid, APP_NT, 0, s>>>(src, dst, n2);
 }
 
-// Per item and operand, the largest entry (negative entries count as 0):
-// scales[op * batch + b].  One workgroup per (item, operand).
-constexpr int MAX_NT = 1024;
+// Per item and operand, the largest entry (negative entries and NaN count as
+// 0), in two stages so that a single large pair spreads over the chip:
+// k_maxscale_part reduces MAXSCALE_PARTS slices of each input to partial
+// maxima, part[(op * batch + b) * MAXSCALE_PARTS + slice]; k_maxscale_final
+// reduces those to scales[op * batch + b].
+constexpr int MAXSCALE_PARTS = 64;
+constexpr int MAX_NT = 256;
+
 template <typename T>
-__global__ __launch_bounds__(MAX_NT) void k_maxscale(const T* __restrict__ x, const T* __restrict__ y,
-                                                     uint64_t n2, T* __restrict__ scales)
+__device__ __forceinline__ T block_max(T m, T* red)
 {
-    __shared__ T red[MAX_NT];
-    const T* src = (blockIdx.y ? y : x) + (uint64_t)blockIdx.x * n2;
-    T m = T(0);
-    for (uint64_t i = threadIdx.x; i < n2; i += MAX_NT) {
-        const T v = src[i];
-        m = v > m ? v : m;
-    }
     red[threadIdx.x] = m;
     __syncthreads();
     for (int h = MAX_NT / 2; h > 0; h >>= 1) {
-        if ((int)threadIdx.x < h) red[threadIdx.x] = red[threadIdx.x + h] > red[threadIdx.x] ? red[threadIdx.x + h]
-                                                                                              : red[threadIdx.x];
+        if ((int)threadIdx.x < h && red[threadIdx.x + h] > red[threadIdx.x]) red[threadIdx.x] = red[threadIdx.x + h];
         __syncthreads();
     }
-    if (threadIdx.x == 0) scales[(uint64_t)blockIdx.y * gridDim.x + blockIdx.x] = red[0];
+    return red[0];
+}
+
+// grid (MAXSCALE_PARTS, batch, 2): blockIdx.y = item, blockIdx.z = operand
+template <typename T>
+__global__ __launch_bounds__(MAX_NT) void k_maxscale_part(const T* __restrict__ x, const T* __restrict__ y,
+                                                          uint64_t n2, T* __restrict__ part)
+{
+    __shared__ T red[MAX_NT];
+    const T* src = (blockIdx.z ? y : x) + (uint64_t)blockIdx.y * n2;
+    T m = T(0);
+    for (uint64_t i = (uint64_t)blockIdx.x * MAX_NT + threadIdx.x; i < n2; i += (uint64_t)MAXSCALE_PARTS * MAX_NT) {
+        const T v = src[i];
+        m = v > m ? v : m;
+    }
+    m = block_max(m, red);
+    if (threadIdx.x == 0)
+        part[((uint64_t)blockIdx.z * gridDim.y + blockIdx.y) * MAXSCALE_PARTS + blockIdx.x] = m;
+}
+
+// grid (batch, 2)
+template <typename T>
+__global__ __launch_bounds__(MAX_NT) void k_maxscale_final(const T* __restrict__ part, T* __restrict__ scales)
+{
+    __shared__ T red[MAX_NT];
+    const uint64_t row = (uint64_t)blockIdx.y * gridDim.x + blockIdx.x;
+    T m = T(0);
+    for (int i = threadIdx.x; i < MAXSCALE_PARTS; i += MAX_NT) {
+        const T v = part[row * MAXSCALE_PARTS + i];
+        m = v > m ? v : m;
+    }
+    m = block_max(m, red);
+    if (threadIdx.x == 0) scales[row] = m;
 }
 
 template <typename T>
@@ -218,19 +246,27 @@ __global__ __launch_bounds__(APP_NT) void k_root(T* __restrict__ z, const T* __r
     }
 }
 
+// Scales (2 per item) followed by the partial maxima (2 * MAXSCALE_PARTS per item).
+static size_t maxconv_scale_bytes(int batch, size_t es)
+{
+    return round256(2 * (size_t)batch * (1 + MAXSCALE_PARTS) * es);
+}
+
 template <typename T>
 static int maxconv_t(const T* x, const T* y, T* z, int D, int batch, double p, bool round, char* ws,
                      size_t ws_bytes, int cus, hipStream_t s)
 {
     const uint64_t n2 = 1ull << D, n3 = pow3u(D);
     T* scales = reinterpret_cast<T*>(ws);
-    const size_t sc_b = round256(2 * (size_t)batch * sizeof(T));
+    const size_t sc_b = maxconv_scale_bytes(batch, sizeof(T));
     const size_t op_b = round256((size_t)batch * n2 * sizeof(T));
+    T* part = scales + 2 * (size_t)batch;
     T* xp = reinterpret_cast<T*>(ws + sc_b);
     T* yp = reinterpret_cast<T*>(ws + sc_b + op_b);
     {
         LaunchScope scope(s, 2.0 * batch * n2 * sizeof(T), "maxscale<%s>", tname<T>());
-        k_maxscale<T><<<dim3(batch, 2, 1), MAX_NT, 0, s>>>(x, y, n2, scales);
+        k_maxscale_part<T><<<dim3(MAXSCALE_PARTS, batch, 2), MAX_NT, 0, s>>>(x, y, n2, part);
+        k_maxscale_final<T><<<dim3(batch, 2, 1), MAX_NT, 0, s>>>(part, scales);
     }
     {
         LaunchScope scope(s, 4.0 * batch * n2 * sizeof(T), "power<%s>", tname<T>());
@@ -392,7 +428,7 @@ size_t hc_maxconv_workspace_bytes(int D, int dtype, int batch)
 {
     if (D < 0 || D > HC_MAX_D || (dtype != HC_F64 && dtype != HC_F32) || batch < 1) return (size_t)-1;
     const size_t es = dtype_size(dtype);
-    return round256(2 * (size_t)batch * es) + 2 * round256((size_t)batch * ((size_t)1 << D) * es) +
+    return maxconv_scale_bytes(batch, es) + 2 * round256((size_t)batch * ((size_t)1 << D) * es) +
            hc_workspace_bytes(D, dtype, batch);
 }
 
