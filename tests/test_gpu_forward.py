@@ -95,6 +95,25 @@ def test_uniform_batch(dtype):
         check(Z[b], oracle.canonical(x, y), f"batch item {b}")
 
 
+@pytest.mark.parametrize("D", [3, 9])
+def test_maximum_batch(D):
+    """65535 items, the largest batch (grid y): D = 3 runs as one fused tile
+    per item, D = 9 adds an outer forward and an inverse pass; the first, the
+    last and 62 sampled items are checked bitwise against the oracle."""
+    B = 65535
+    g = np.random.default_rng([hc_inputs.SEED, 91, D])
+    X = g.random((B, 1 << D))
+    Y = g.random((B, 1 << D))
+    Z = hc.convolve_batch(on_gpu(X), on_gpu(Y))
+    torch.cuda.synchronize(DEV)
+    items = np.unique(np.concatenate([[0, B - 1], g.choice(B, 62, replace=False)]))
+    Zs = Z[torch.from_numpy(items).to(DEV)].cpu().numpy()
+    for row, b in enumerate(items):
+        check(Zs[row], oracle.canonical(X[b], Y[b]), f"item {b} of {B}")
+    del Z
+    torch.cuda.empty_cache()
+
+
 def test_worked_example_and_deltas():
     pins.pin_worked_example(gpu_conv, np.float64)
     for D in (2, 9, 12):
