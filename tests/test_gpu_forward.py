@@ -95,6 +95,17 @@ def test_uniform_batch(dtype):
         check(Z[b], oracle.canonical(x, y), f"batch item {b}")
 
 
+@pytest.mark.parametrize("D", [1, 5, 9, 12])
+def test_int64_full_range_matches_algorithm1(D):
+    """Entries over all of int64: sums, products and outputs overflow, and
+    the GPU's wrapping arithmetic must still equal Algorithm 1 modulo 2^64."""
+    g = np.random.default_rng([hc_inputs.SEED, 96, D])
+    lo, hi = np.iinfo(np.int64).min, np.iinfo(np.int64).max
+    x = g.integers(lo, hi, 1 << D, dtype=np.int64, endpoint=True)
+    y = g.integers(lo, hi, 1 << D, dtype=np.int64, endpoint=True)
+    pins.assert_bitwise(gpu_conv(x, y), oracle.naive(x, y), f"D={D} full-range int64")
+
+
 @pytest.mark.parametrize("D", [3, 9])
 def test_maximum_batch(D):
     """65535 items, the largest batch (grid y): D = 3 runs as one fused tile

@@ -6,6 +6,7 @@ trustworthy before any GPU result is compared with it.
 import numpy as np
 import pytest
 
+import hc_inputs
 import oracle
 from tests import pins
 
@@ -243,3 +244,38 @@ def test_adjoint_all_ones(dtype):
     w = np.ones(3 ** D, dtype=dtype)
     gx, gy = oracle.adjoint(x, x.copy(), w)
     assert np.all(gx == 2 ** D) and np.all(gy == 2 ** D)
+
+
+def _wrap64(v: int) -> int:
+    v &= (1 << 64) - 1
+    return v - (1 << 64) if v >> 63 else v
+
+
+@pytest.mark.parametrize("impl", EXACT_IMPLS)
+@pytest.mark.parametrize("D", [1, 3, 6])
+def test_int64_full_range_wraps_like_the_ring(impl, D):
+    """Entries spread over all of int64, so that sums, products and the
+    outputs themselves overflow: every implementation agrees with the
+    definition summed in unbounded Python integers and reduced modulo 2^64
+    (the method's identities hold in the ring of integers modulo 2^64)."""
+    g = np.random.default_rng([hc_inputs.SEED, 95, D])
+    x = g.integers(np.iinfo(np.int64).min, np.iinfo(np.int64).max, 1 << D, dtype=np.int64, endpoint=True)
+    y = g.integers(np.iinfo(np.int64).min, np.iinfo(np.int64).max, 1 << D, dtype=np.int64, endpoint=True)
+    ref = [0] * 3 ** D
+    for i in range(1 << D):
+        for j in range(1 << D):
+            k = 0
+            for a in range(D - 1, -1, -1):
+                k = 3 * k + ((i >> a) & 1) + ((j >> a) & 1)
+            ref[k] += int(x[i]) * int(y[j])
+    expect = np.array([_wrap64(v) for v in ref], dtype=np.int64)
+    pins.assert_bitwise(IMPLS[impl](x, y), expect, f"{impl} D={D} full-range int64")
+
+
+def test_int64_wrapping_intermediate_written_out():
+    """D = 1 with x = (2^62, 2^62), y = (1, 0): the forward sum 2^63 wraps,
+    yet z = (2^62, 2^62, 0) exactly."""
+    x = np.array([1 << 62, 1 << 62], dtype=np.int64)
+    y = np.array([1, 0], dtype=np.int64)
+    for name in EXACT_IMPLS:
+        assert IMPLS[name](x, y).tolist() == [1 << 62, 1 << 62, 0], name
