@@ -106,6 +106,20 @@ def test_int64_full_range_matches_algorithm1(D):
     pins.assert_bitwise(gpu_conv(x, y), oracle.naive(x, y), f"D={D} full-range int64")
 
 
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_signed_zeros_and_exact_cancellation(dtype):
+    """Inputs drawn from {-1, -0, +0, 1}: most outputs cancel exactly, and
+    the sign of every zero must match the oracle's order of operations."""
+    D = 10
+    g = np.random.default_rng([hc_inputs.SEED, 97])
+    vals = np.array([-1.0, -0.0, 0.0, 1.0], dtype=dtype)
+    x = vals[g.integers(0, 4, 1 << D)]
+    y = vals[g.integers(0, 4, 1 << D)]
+    ref = oracle.canonical(x, y)
+    assert np.count_nonzero(np.signbit(ref) & (ref == 0)) > 0
+    pins.assert_bitwise(gpu_conv(x, y), ref, "signed zeros")
+
+
 @pytest.mark.parametrize("D", [3, 9])
 def test_maximum_batch(D):
     """65535 items, the largest batch (grid y): D = 3 runs as one fused tile
