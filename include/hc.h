@@ -298,6 +298,10 @@ int hc_difference_batch(const void* x, const void* y, void* z, int D, int dtype,
  * HC_ERR_INVALID_ARG for p or unknown flags.
  */
 #define HC_MAXCONV_ROUND 1u
+/* Run the root as a kernel of its own after the convolution instead of in
+ * the convolution's last inverse pass (same results, bit for bit; for
+ * testing and measurement). */
+#define HC_MAXCONV_SEPARATE_ROOT 2u
 size_t hc_maxconv_workspace_bytes(int D, int dtype, int batch);  /* (size_t)-1 if invalid */
 int hc_maxconv_pnorm_batch(const void* x, const void* y, void* z, int D, int dtype, int batch, double p,
                            unsigned flags, void* workspace, size_t workspace_bytes, hipStream_t stream);

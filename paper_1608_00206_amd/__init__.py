@@ -250,10 +250,13 @@ def difference(x: torch.Tensor, y: torch.Tensor, out: torch.Tensor | None = None
 
 
 def maxconv_pnorm_batch(x: torch.Tensor, y: torch.Tensor, p: float, round: bool = False,
-                        out: torch.Tensor | None = None, workspace: torch.Tensor | None = None) -> torch.Tensor:
+                        out: torch.Tensor | None = None, workspace: torch.Tensor | None = None,
+                        separate_root: bool = False) -> torch.Tensor:
     """p-norm estimate of the max-convolution max x[i] y[j] of nonnegative
     (B, 2^D) float64/float32 inputs: (sum (x[i] y[j])^p)^(1/p) per output;
-    round=True rounds the estimates to integers.  Returns (B, 3^D)."""
+    round=True rounds the estimates to integers.  separate_root=True runs the
+    root as its own kernel rather than in the convolution's last pass (same
+    bits).  Returns (B, 3^D)."""
     if x.dim() != 2 or x.shape != y.shape:
         raise ValueError("x and y must both have shape (B, 2^D)")
     if x.dtype != y.dtype:
@@ -273,20 +276,22 @@ def maxconv_pnorm_batch(x: torch.Tensor, y: torch.Tensor, p: float, round: bool 
         raise TypeError("the p-norm max-convolution supports float64 and float32")
     ws = _workspace(nbytes, x.device, workspace)
     _launch(x.device, _abi.hc_maxconv_pnorm_batch, x.data_ptr(), y.data_ptr(), out.data_ptr(), D, code, B, float(p),
-            _abi.HC_MAXCONV_ROUND if round else 0, ws.data_ptr(), nbytes,
+            (_abi.HC_MAXCONV_ROUND if round else 0) | (_abi.HC_MAXCONV_SEPARATE_ROOT if separate_root else 0),
+            ws.data_ptr(), nbytes,
             _stream(x.device))
     return out
 
 
 def maxconv_pnorm(x: torch.Tensor, y: torch.Tensor, p: float, round: bool = False,
-                  out: torch.Tensor | None = None, workspace: torch.Tensor | None = None) -> torch.Tensor:
+                  out: torch.Tensor | None = None, workspace: torch.Tensor | None = None,
+                  separate_root: bool = False) -> torch.Tensor:
     """Single-pair form of maxconv_pnorm_batch: (2^D,) inputs, (3^D,) output."""
     if x.dim() != 1 or x.shape != y.shape:
         raise ValueError("x and y must be 1-D tensors of the same length 2^D")
     D = dim_of(x.numel())
     flat = out.view(1, 3 ** D) if out is not None else None
-    return maxconv_pnorm_batch(x.view(1, -1), y.view(1, -1), p, round=round, out=flat,
-                               workspace=workspace).view(3 ** D)
+    return maxconv_pnorm_batch(x.view(1, -1), y.view(1, -1), p, round=round, out=flat, workspace=workspace,
+                               separate_root=separate_root).view(3 ** D)
 
 
 class HypercubeConv(torch.autograd.Function):

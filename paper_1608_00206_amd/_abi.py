@@ -175,6 +175,7 @@ def hc_difference_batch(x: int, y: int, z: int, D: int, dtype: int, batch: int, 
 
 
 HC_MAXCONV_ROUND = 1
+HC_MAXCONV_SEPARATE_ROOT = 2
 
 
 def hc_maxconv_workspace_bytes(D: int, dtype: int, batch: int = 1) -> int:

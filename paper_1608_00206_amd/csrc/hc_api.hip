@@ -316,7 +316,7 @@ int launch_fwd_adj_pass(int M, const T* in0, const T* in1, T* out0, T* out1, BMa
 // rounded up to a multiple of 8 so that the XCD-aware walk hands every XCD
 // one contiguous chunk.  per_cu > 0: a persistent grid of at most that many
 // workgroups per CU, each looping over tiles.
-static uint32_t tile_grid(uint64_t n_tiles, int cus, int per_cu)
+uint32_t tile_grid(uint64_t n_tiles, int cus, int per_cu)
 {
     uint64_t g = n_tiles;
     if (per_cu > 0) {
@@ -450,7 +450,7 @@ int launch_pass(const InvPass& ip, const T* src, T* dst, BMap src_bs, BMap dst_b
 // ------------------------------------------------------------ forward run
 template <typename T>
 int run_forward(const Plan& P, const T* x, const T* y, T* z, int batch, T* ws, int cus, hipStream_t s, BMap x_map,
-                BMap z_map)
+                BMap z_map, const LastPass* last)
 {
     const int D = P.D, K = P.K;
     int rc = HC_OK;
@@ -485,10 +485,19 @@ int run_forward(const Plan& P, const T* x, const T* y, T* z, int batch, T* ws, i
         }
         rc = launch_fused<T>(K, xt, yt, z, P.xt_elems, z_map, (uint32_t)pow3u(P.p), batch, cus, P.grid_per_cu, s);
         if (rc != HC_OK) return rc;
-        for (const InvPass& ip : P.inv) {
+        for (size_t i = 0; i < P.inv.size(); ++i) {
+            const InvPass& ip = P.inv[i];
             const int m = ip.mR + ip.mW;
             const uint64_t L = pow3u(D - ip.a - m);
             const uint32_t n_hi = (uint32_t)pow3u(ip.a);
+            if (last && i + 1 == P.inv.size()) {
+                rc = last->launch(*last, ip, z, z_map, L, n_hi, batch, cus, s);
+                if (rc == HC_OK) {
+                    last->taken = true;
+                    continue;
+                }
+                if (rc != HC_ERR_UNSUPPORTED) return rc;
+            }
             rc = launch_pass<T, false>(ip, z, z, z_map, z_map, L, n_hi, batch, cus, P.grid_per_cu, s);
             if (rc != HC_OK) return rc;
         }
@@ -599,11 +608,11 @@ int run_backward(const Plan& P, const T* x, const T* y, const T* gz, uint64_t gz
 }
 
 template int run_forward<double>(const Plan&, const double*, const double*, double*, int, double*, int, hipStream_t,
-                                 BMap, BMap);
+                                 BMap, BMap, const LastPass*);
 template int run_forward<float>(const Plan&, const float*, const float*, float*, int, float*, int, hipStream_t, BMap,
-                                BMap);
+                                BMap, const LastPass*);
 template int run_forward<uint64_t>(const Plan&, const uint64_t*, const uint64_t*, uint64_t*, int, uint64_t*, int,
-                                   hipStream_t, BMap, BMap);
+                                   hipStream_t, BMap, BMap, const LastPass*);
 template int run_backward<double>(const Plan&, const double*, const double*, const double*, uint64_t, double*,
                                   double*, int, double*, int, hipStream_t);
 template int run_backward<float>(const Plan&, const float*, const float*, const float*, uint64_t, float*, float*,
@@ -655,6 +664,14 @@ size_t hc_backward_workspace_bytes(int D, int dtype, int batch)
 int hc_convolve_batch(const void* x, const void* y, void* z, int D, int dtype, int batch, void* workspace,
                       size_t workspace_bytes, hipStream_t stream)
 {
+    return convolve_batch_last(x, y, z, D, dtype, batch, workspace, workspace_bytes, stream, nullptr);
+}
+
+}  // extern "C"
+
+int hc::convolve_batch_last(const void* x, const void* y, void* z, int D, int dtype, int batch, void* workspace,
+                            size_t workspace_bytes, hipStream_t stream, const LastPass* last)
+{
     g_last_error.clear();
     if (!x || !y || !z) return fail(HC_ERR_INVALID_ARG, "x, y and z must be non-null");
     if (D < 0 || D > HC_MAX_D) return fail(HC_ERR_D_RANGE, "D=%d outside [0, %d]", D, HC_MAX_D);
@@ -682,15 +699,17 @@ int hc_convolve_batch(const void* x, const void* y, void* z, int D, int dtype, i
     switch (dtype) {
         case HC_F64:
             return run_forward<double>(P, (const double*)x, (const double*)y, (double*)z, batch, (double*)workspace,
-                                       cus, stream, P.n2, P.n3);
+                                       cus, stream, P.n2, P.n3, last);
         case HC_F32:
             return run_forward<float>(P, (const float*)x, (const float*)y, (float*)z, batch, (float*)workspace, cus,
-                                      stream, P.n2, P.n3);
+                                      stream, P.n2, P.n3, last);
         default:
             return run_forward<uint64_t>(P, (const uint64_t*)x, (const uint64_t*)y, (uint64_t*)z, batch,
-                                         (uint64_t*)workspace, cus, stream, P.n2, P.n3);
+                                         (uint64_t*)workspace, cus, stream, P.n2, P.n3, last);
     }
 }
+
+extern "C" {
 
 int hc_convolve(const void* x, const void* y, void* z, int D, int dtype, void* workspace, size_t workspace_bytes,
                 hipStream_t stream)

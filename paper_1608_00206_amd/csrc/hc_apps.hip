@@ -25,6 +25,7 @@
 
 #include "hc.h"
 #include "hc_internal.hpp"
+#include "hc_kernels.hpp"
 
 namespace hc {
 
@@ -211,6 +212,22 @@ __device__ __forceinline__ double root_int(double v, int p, const RootCoef& rc)
 // 1 + |ln v| / p.  Either error is far below the estimate's own 2^(s/p) bias.
 enum RootMode { ROOT_NONE = 0, ROOT_INT = 1, ROOT_EXPLOG = 2 };
 
+// mx my max(v, 0)^(1/p) for one output (s = mx my), optionally rounded.
+template <typename T, int MODE>
+__device__ __forceinline__ T root_value(T v, T s, T inv_p, int ip, const RootCoef& rc, int round)
+{
+    T r = T(0);
+    if (v > T(0)) {
+        T w;
+        if constexpr (MODE == ROOT_NONE) w = v;
+        else if constexpr (MODE == ROOT_INT) w = (T)root_int((double)v, ip, rc);
+        else w = exp_t<T>(log_t<T>(v) * inv_p);
+        r = s * w;
+    }
+    if (round) r = rint(r);
+    return r;
+}
+
 constexpr int ROOT_U = 4;
 constexpr uint64_t ROOT_SPAN = (uint64_t)ROOT_U * APP_NT;
 
@@ -235,17 +252,57 @@ __global__ __launch_bounds__(APP_NT) void k_root(T* __restrict__ z, const T* __r
 #pragma unroll
     for (int q = 0; q < ROOT_U; ++q) {
         const uint64_t k = k0 + q * APP_NT;
-        T r = T(0);
-        if (v[q] > T(0)) {
-            T w;
-            if constexpr (MODE == ROOT_NONE) w = v[q];
-            else if constexpr (MODE == ROOT_INT) w = (T)root_int((double)v[q], ip, rc);
-            else w = exp_t<T>(log_t<T>(v[q]) * inv_p);
-            r = s * w;
-        }
-        if (round) r = rint(r);
+        const T r = root_value<T, MODE>(v[q], s, inv_p, ip, rc, round);
         if (k < n3) z[off + k] = r;
     }
+}
+
+// The root as the epilogue of the convolution's last inverse pass: every
+// entry of the pass's tile goes through root_value before it is stored, so
+// the separate read and write of z by k_root disappear.  bind() fixes the
+// batch item's scale.
+template <typename T, int MODE>
+struct RootEpilogue {
+    const T* scales;
+    int batch;
+    T inv_p;
+    int ip;
+    RootCoef rc;
+    int round;
+    struct Bound {
+        static constexpr bool ALL = true;
+        T s, inv_p;
+        int ip;
+        RootCoef rc;
+        int round;
+        __device__ __forceinline__ T apply(T v) const { return root_value<T, MODE>(v, s, inv_p, ip, rc, round); }
+    };
+    __device__ __forceinline__ Bound bind(uint32_t b) const
+    {
+        return Bound{scales[b] * scales[batch + b], inv_p, ip, rc, round};
+    }
+};
+
+// LastPass::launch for the root: the streamed-thirds passes (4 register and
+// 1 or 2 wave axes) have an epilogue kernel; other shapes decline.
+template <typename T, int MODE>
+static int launch_root_pass(const LastPass& self, const InvPass& ip, void* z, BMap z_map, uint64_t L,
+                            uint32_t n_hi, int batch, int cus, hipStream_t s)
+{
+    if (ip.mR != 4 || (ip.mW != 1 && ip.mW != 2)) return HC_ERR_UNSUPPORTED;
+    const RootEpilogue<T, MODE>& epi = *static_cast<const RootEpilogue<T, MODE>*>(self.ctx);
+    const uint32_t tiles_per_hi = (uint32_t)((L + 63) / 64);
+    const uint64_t n_tiles = (uint64_t)tiles_per_hi * n_hi;
+    const dim3 grid(tile_grid(n_tiles, cus, 0), batch, 1);
+    const int TM = (int)pow3u(4 + ip.mW);
+    LaunchScope scope(s, 2.0 * batch * n_hi * L * TM * sizeof(T), "inv_pass_root<%s,4+%d>", tname<T>(), ip.mW);
+    if (ip.mW == 2)
+        k_inv_pass_epi<T, 2, RootEpilogue<T, MODE>><<<grid, 64 * 9, 0, s>>>((T*)z, z_map, L, tiles_per_hi,
+                                                                           (uint32_t)n_tiles, epi);
+    else
+        k_inv_pass_epi<T, 1, RootEpilogue<T, MODE>><<<grid, 64 * 3, 0, s>>>((T*)z, z_map, L, tiles_per_hi,
+                                                                           (uint32_t)n_tiles, epi);
+    return HC_OK;
 }
 
 // Scales (2 per item) followed by the partial maxima (2 * MAXSCALE_PARTS per item).
@@ -255,8 +312,8 @@ static size_t maxconv_scale_bytes(int batch, size_t es)
 }
 
 template <typename T>
-static int maxconv_t(const T* x, const T* y, T* z, int D, int batch, double p, bool round, char* ws,
-                     size_t ws_bytes, int cus, hipStream_t s)
+static int maxconv_t(const T* x, const T* y, T* z, int D, int batch, double p, bool round, bool separate_root,
+                     char* ws, size_t ws_bytes, int cus, hipStream_t s)
 {
     const uint64_t n2 = 1ull << D, n3 = pow3u(D);
     T* scales = reinterpret_cast<T*>(ws);
@@ -276,25 +333,42 @@ static int maxconv_t(const T* x, const T* y, T* z, int D, int batch, double p, b
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "max-convolution launch");
-    const int rc = hc_convolve_batch(xp, yp, z, D, sizeof(T) == 4 ? HC_F32 : HC_F64, batch, ws + sc_b + 2 * op_b,
-                                     ws_bytes - sc_b - 2 * op_b, s);
+    const int ip = (p == std::floor(p) && p >= 2 && p <= ROOT_INT_MAX) ? (int)p : 0;
+    RootCoef coef{};
+    const double c1 = 1.0 / p;
+    coef.c[0] = c1;
+    coef.c[1] = coef.c[0] * (c1 - 1) / 2;
+    coef.c[2] = coef.c[1] * (c1 - 2) / 3;
+    coef.c[3] = coef.c[2] * (c1 - 3) / 4;
+    coef.inv_pf = (float)c1;
+    const T inv_p = (T)c1;
+    const int rnd = round ? 1 : 0;
+    const int mode = p == 1 ? ROOT_NONE : (ip ? ROOT_INT : ROOT_EXPLOG);
+    // the root runs as the epilogue of the convolution's last inverse pass
+    // where that pass has an epilogue kernel, else as its own kernel
+    const RootEpilogue<T, ROOT_NONE> e_none{scales, batch, inv_p, ip, coef, rnd};
+    const RootEpilogue<T, ROOT_INT> e_int{scales, batch, inv_p, ip, coef, rnd};
+    const RootEpilogue<T, ROOT_EXPLOG> e_explog{scales, batch, inv_p, ip, coef, rnd};
+    LastPass last;
+    if (mode == ROOT_NONE) {
+        last.launch = launch_root_pass<T, ROOT_NONE>;
+        last.ctx = &e_none;
+    } else if (mode == ROOT_INT) {
+        last.launch = launch_root_pass<T, ROOT_INT>;
+        last.ctx = &e_int;
+    } else {
+        last.launch = launch_root_pass<T, ROOT_EXPLOG>;
+        last.ctx = &e_explog;
+    }
+    const int rc = convolve_batch_last(xp, yp, z, D, sizeof(T) == 4 ? HC_F32 : HC_F64, batch, ws + sc_b + 2 * op_b,
+                                       ws_bytes - sc_b - 2 * op_b, s, separate_root ? nullptr : &last);
     if (rc != HC_OK) return rc;
-    {
+    if (!last.taken) {
         LaunchScope scope(s, 2.0 * batch * n3 * sizeof(T), "root<%s>", tname<T>());
-        const int ip = (p == std::floor(p) && p >= 2 && p <= ROOT_INT_MAX) ? (int)p : 0;
-        RootCoef rc{};
-        const double c1 = 1.0 / p;
-        rc.c[0] = c1;
-        rc.c[1] = rc.c[0] * (c1 - 1) / 2;
-        rc.c[2] = rc.c[1] * (c1 - 2) / 3;
-        rc.c[3] = rc.c[2] * (c1 - 3) / 4;
-        rc.inv_pf = (float)c1;
         const dim3 grid((uint32_t)((n3 + ROOT_SPAN - 1) / ROOT_SPAN), batch, 1);
-        const T inv_p = (T)c1;
-        const int rnd = round ? 1 : 0;
-        if (p == 1) k_root<T, ROOT_NONE><<<grid, APP_NT, 0, s>>>(z, scales, n3, inv_p, ip, rc, rnd);
-        else if (ip) k_root<T, ROOT_INT><<<grid, APP_NT, 0, s>>>(z, scales, n3, inv_p, ip, rc, rnd);
-        else k_root<T, ROOT_EXPLOG><<<grid, APP_NT, 0, s>>>(z, scales, n3, inv_p, ip, rc, rnd);
+        if (mode == ROOT_NONE) k_root<T, ROOT_NONE><<<grid, APP_NT, 0, s>>>(z, scales, n3, inv_p, ip, coef, rnd);
+        else if (mode == ROOT_INT) k_root<T, ROOT_INT><<<grid, APP_NT, 0, s>>>(z, scales, n3, inv_p, ip, coef, rnd);
+        else k_root<T, ROOT_EXPLOG><<<grid, APP_NT, 0, s>>>(z, scales, n3, inv_p, ip, coef, rnd);
     }
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "max-convolution launch");
@@ -443,7 +517,8 @@ int hc_maxconv_pnorm_batch(const void* x, const void* y, void* z, int D, int dty
         return fail(HC_ERR_UNSUPPORTED, "the p-norm max-convolution supports float64 and float32 only");
     if (batch < 1 || batch > 65535) return fail(HC_ERR_INVALID_ARG, "batch=%d outside [1, 65535]", batch);
     if (!(p >= 1.0) || !(p <= 1e300)) return fail(HC_ERR_INVALID_ARG, "p must be a finite number >= 1");
-    if (flags & ~HC_MAXCONV_ROUND) return fail(HC_ERR_INVALID_ARG, "unknown flags 0x%x", flags);
+    if (flags & ~(HC_MAXCONV_ROUND | HC_MAXCONV_SEPARATE_ROOT))
+        return fail(HC_ERR_INVALID_ARG, "unknown flags 0x%x", flags);
     const size_t es = dtype_size(dtype);
     if (misaligned(x, es) || misaligned(y, es) || misaligned(z, es) || misaligned(workspace, 16))
         return fail(HC_ERR_MISALIGNED, "data must be aligned to the element size, the workspace to 16 bytes");
@@ -462,12 +537,13 @@ int hc_maxconv_pnorm_batch(const void* x, const void* y, void* z, int D, int dty
     int rc = device_cus(&cus);
     if (rc != HC_OK) return rc;
     const bool round = (flags & HC_MAXCONV_ROUND) != 0;
+    const bool separate = (flags & HC_MAXCONV_SEPARATE_ROOT) != 0;
     char* ws = static_cast<char*>(workspace);
     if (dtype == HC_F64)
-        return maxconv_t<double>((const double*)x, (const double*)y, (double*)z, D, batch, p, round, ws,
+        return maxconv_t<double>((const double*)x, (const double*)y, (double*)z, D, batch, p, round, separate, ws,
                                  workspace_bytes, cus, stream);
-    return maxconv_t<float>((const float*)x, (const float*)y, (float*)z, D, batch, p, round, ws, workspace_bytes,
-                            cus, stream);
+    return maxconv_t<float>((const float*)x, (const float*)y, (float*)z, D, batch, p, round, separate, ws,
+                            workspace_bytes, cus, stream);
 }
 
 }  // extern "C"

@@ -84,11 +84,31 @@ PlanOpts default_opts();
 size_t plan_ws_bytes(const Plan& P, int batch);
 size_t plan_bwd_ws_bytes(const Plan& P, int batch);
 
+// Workgroups for n_tiles tiles (one per tile when per_cu == 0, else a
+// persistent grid of at most per_cu workgroups per CU).
+uint32_t tile_grid(uint64_t n_tiles, int cus, int per_cu);
+
+// A replacement for the last outer inverse pass of a forward run that fuses
+// an elementwise step into it.  launch() either enqueues that pass and
+// returns HC_OK, or returns HC_ERR_UNSUPPORTED for a pass shape it has no
+// kernel for, and the plain pass runs instead; `taken` records which.  A
+// plan without outer passes never calls it.
+struct LastPass {
+    int (*launch)(const LastPass& self, const InvPass& ip, void* z, BMap z_map, uint64_t L, uint32_t n_hi,
+                  int batch, int cus, hipStream_t s) = nullptr;
+    const void* ctx = nullptr;
+    mutable bool taken = false;
+};
+
 // Forward path for `batch` items of one D; x_map / z_map give each item's
 // element offset in x, y and z (uniform strides or per-item tables).
 template <typename T>
 int run_forward(const Plan& P, const T* x, const T* y, T* z, int batch, T* ws, int cus, hipStream_t s, BMap x_map,
-                BMap z_map);
+                BMap z_map, const LastPass* last = nullptr);
+
+// hc_convolve_batch with an optional replacement of its last inverse pass.
+int convolve_batch_last(const void* x, const void* y, void* z, int D, int dtype, int batch, void* workspace,
+                        size_t workspace_bytes, hipStream_t stream, const LastPass* last);
 template <typename T>
 int run_backward(const Plan& P, const T* x, const T* y, const T* gz, uint64_t gz_bs, T* gx, T* gy, int batch,
                  T* ws, int cus, hipStream_t s);

@@ -356,6 +356,16 @@ __device__ __forceinline__ void inv_tile(const T* src, T* dst, uint64_t L, uint3
     }
 }
 
+// Epilogue of a final inverse pass: NoEpilogue stores the entries the map
+// changes, as above.  An epilogue with ALL = true maps every entry of the
+// tile through apply() and stores them all (used to fuse an elementwise step
+// that follows the convolution into its last pass).
+struct NoEpilogue {
+    static constexpr bool ALL = false;
+    template <typename T>
+    __device__ __forceinline__ T apply(T v) const { return v; }
+};
+
 // One tile of an inverse pass with mR = 4 and a wave part (CW = 1, every wave
 // active).  The 81 register values of a lane would not fit the register budget
 // of a 3^mW-wave workgroup, so the register sub-cube is streamed in thirds of
@@ -368,9 +378,9 @@ __device__ __forceinline__ void inv_tile(const T* src, T* dst, uint64_t L, uint3
 // Each third crosses to the wave part through three LDS sub-round buffers
 // ([3][tW][9][64]); third 1 is loaded while the first third is being stored.
 // Every entry sees the same operations in the same order as in inv_tile.
-template <typename T, int mW, bool ADJ, bool IN_PLACE>
+template <typename T, int mW, bool ADJ, bool IN_PLACE, class E = NoEpilogue>
 __device__ __forceinline__ void inv_tile_r4(const T* src, T* dst, uint64_t L, uint32_t hi, uint32_t j, int wave,
-                                            T* S)
+                                            T* S, const E& epi = E{})
 {
     constexpr int tR = 81, TH = 27, tW = pow3c(mW), TM = tR * tW;
     constexpr int SG = 9;                       // register indices per sub-round
@@ -440,7 +450,8 @@ __device__ __forceinline__ void inv_tile_r4(const T* src, T* dst, uint64_t L, ui
                             changed = !(d0 == 1 && sr == 1 && k_all && all_digits_one(gW, mW));
                         else
                             changed = d0 == 1 || sr == 1 || k_one || has_digit_one(gW, mW);
-                        if (changed || !IN_PLACE) buf_store<T>(row_rsrc(wp, seg_bytes), col_off, u[gW]);
+                        if constexpr (E::ALL) buf_store<T>(row_rsrc(wp, seg_bytes), col_off, epi.apply(u[gW]));
+                        else if (changed || !IN_PLACE) buf_store<T>(row_rsrc(wp, seg_bytes), col_off, u[gW]);
                         wp += step;
                     }
                 }
@@ -537,6 +548,26 @@ __global__ __launch_bounds__(64 * pow3c(mW) * CW) void k_inv_pass(const T* src, 
             if constexpr (mW > 0) lds_barrier();  // the previous tile's phase-2 reads are done
             inv_tile<T, mR, mW, CW, ADJ, IN_PLACE>(src, dst, L, hi, j, wave, S);
         }
+    }
+}
+
+// The last inverse pass of a forward run with an epilogue: the in-place
+// streamed-thirds tile (mR = 4, 0 < mW), every entry mapped through
+// epi.bind(item).apply() and stored.  One tile per workgroup.
+template <typename T, int mW, class EP>
+__global__ __launch_bounds__(64 * pow3c(mW)) void k_inv_pass_epi(T* z, BMap z_map, uint64_t L,
+                                                                 uint32_t tiles_per_hi, uint32_t n_tiles, EP epi)
+{
+    using P = PassCfg<4, mW, 1>;
+    static_assert(P::THIRDS, "epilogues run on the streamed-thirds tile");
+    __shared__ T S[P::LDS];
+    z += z_map.at(blockIdx.y);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const TileWalk walk = xcd_tile_walk(n_tiles);
+    if (walk.first < walk.end) {
+        const uint32_t hi = walk.first / tiles_per_hi;
+        const auto e = epi.bind(blockIdx.y);
+        inv_tile_r4<T, mW, false, true>(z, z, L, hi, walk.first - hi * tiles_per_hi, wave, S, e);
     }
 }
 

@@ -146,7 +146,7 @@ def test_application_errors():
 
 # ------------------------------------------------- p-norm max-convolution
 
-def pnorm_tolerance(x, y, p, D, z_ref, dtype):
+def pnorm_tolerance(x, y, p, D, z_ref, dtype, ks=None):
     """Per-output tolerance of the GPU estimate against the exact p-norm.
 
     With zp = (z_ref / (mx my))^p the exact powered convolution, the GPU's
@@ -166,7 +166,7 @@ def pnorm_tolerance(x, y, p, D, z_ref, dtype):
     mx, my = float(x.max()), float(y.max())
     xp = (x.astype(np.float64) / mx) ** p
     yp = (y.astype(np.float64) / my) ** p
-    Bp = oracle.bound(xp, yp)
+    Bp = oracle.bound(xp, yp) if ks is None else oracle.bound_at(xp, yp, ks)
     zp = (z_ref / (mx * my)) ** p
     E = (2 * p + 5) * u * zp + (4 * D + 2) * u * Bp + (4 * D + 2) * (1 << D) * tiny
     r = zp ** (1.0 / p)
@@ -275,6 +275,54 @@ def test_maxconv_root_accuracy_over_wide_range(dtype, p):
         bound = (4 + 3 / p + 4 * np.abs(np.log(zp)) / p) * u
     assert np.all(rel <= bound), f"worst {np.max(rel / u):.3f} u"
     print(f"p={p} {np.dtype(dtype).name}: worst {np.max(rel) / u:.3f} u over z' down to {zp.min():.3g}")
+
+
+def _kernel_names(fn):
+    torch.cuda.synchronize(DEV)
+    hc._abi.hc_profile_collect()
+    hc._abi.hc_profile_enable(True)
+    try:
+        out = fn()
+        torch.cuda.synchronize(DEV)
+    finally:
+        hc._abi.hc_profile_enable(False)
+    return out, [st[0] for st in hc._abi.hc_profile_collect()]
+
+
+@pytest.mark.parametrize("D,dtype,fused", [(13, np.float64, True), (14, np.float64, True), (15, np.float64, False),
+                                           (14, np.float32, True), (15, np.float32, True)])
+@pytest.mark.parametrize("p", [1.0, 32.0, 7.5])
+def test_maxconv_root_in_last_pass_matches_separate_root(D, dtype, fused, p):
+    """Where the convolution's last inverse pass is a streamed-thirds pass (4
+    register and 1 or 2 wave axes) the root runs as its epilogue; the bits
+    equal those of the separate root kernel, for every root form, with and
+    without rounding, over a batch of 3 (per-item scales).  Other last
+    passes (D=15 float64: one axis) fall back to the separate kernel."""
+    B = 3
+    pairs = [hc_inputs.random_pair(D, dtype, 30 + b) for b in range(B)]
+    X = on_gpu(np.stack([a for a, _ in pairs]))
+    Y = on_gpu(np.stack([b for _, b in pairs]))
+    for rnd in (False, True):
+        a, names = _kernel_names(lambda: hc.maxconv_pnorm_batch(X, Y, p, round=rnd))
+        b, names_sep = _kernel_names(lambda: hc.maxconv_pnorm_batch(X, Y, p, round=rnd, separate_root=True))
+        assert any(n.startswith("inv_pass_root") for n in names) == fused, names
+        assert not any(n.startswith("inv_pass_root") for n in names_sep), names_sep
+        iv = torch.int64 if np.dtype(dtype) == np.float64 else torch.int32
+        assert torch.equal(a.view(iv), b.view(iv)), f"D={D} p={p} round={rnd}"
+
+
+def test_maxconv_root_in_last_pass_matches_oracle_sampled():
+    """D = 14 float64, p = 32, the root in the last pass: sampled outputs
+    against the oracle's p-norm within the error model's tolerance."""
+    D, p = 14, 32.0
+    x, y = hc_inputs.random_pair(D, np.float64, 41)
+    z = hc.maxconv_pnorm(on_gpu(x), on_gpu(y), p).cpu().numpy()
+    g = np.random.default_rng([hc_inputs.SEED, 98])
+    ks = np.unique(np.concatenate([[0, 3 ** D - 1], g.integers(0, 3 ** D, 3000)])).astype(np.uint64)
+    ref = oracle.pnorm_at(x, y, p, ks)
+    tol, _ = pnorm_tolerance(x, y, p, D, ref, np.float64, ks=ks)
+    err = np.abs(z[ks.astype(np.int64)] - ref)
+    assert np.all(err <= tol), f"max excess {np.max(err - tol)}"
 
 
 def test_maxconv_batch_and_errors():
