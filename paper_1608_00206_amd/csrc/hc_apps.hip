@@ -18,9 +18,10 @@
 //     inverse map (relative error ~ (4D+2) u B/z' of the powered result)
 //     dominates.  Optionally rounded to integers.
 //
-// All three reuse hc_convolve_batch unchanged; the new device work is a
-// padding, reflecting or powering copy into the caller's workspace (and the
-// root of the p-norm in place on z).
+// All three reuse the forward path unchanged; the new device work is a
+// padding, reflecting or powering copy into the caller's workspace, and the
+// root of the p-norm, which runs as the epilogue of the convolution's last
+// inverse pass where that pass has an epilogue kernel, else in place on z.
 #include <cmath>
 
 #include "hc.h"
