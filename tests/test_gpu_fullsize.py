@@ -258,3 +258,29 @@ def test_d21_f64_maximum_size_sampled():
     say(f"D=21 float64: max |err|/(u B) over {ks.size} sampled outputs = {r:.2f}; sum z - 1 = {total - 1:.2e}")
     del z
     torch.cuda.empty_cache()
+
+
+def test_maxconv_d20_root_in_last_pass():
+    """The benchmark's p-norm max-convolution (D = 20 float64, p = 32, the
+    root in the last inverse pass): bitwise equal to the separate root kernel
+    on the GPU, and sampled outputs within the error model's tolerance of the
+    oracle's p-norm."""
+    from tests.test_gpu_apps import pnorm_tolerance
+    D, p = 20, 32.0
+    x, y = hc_inputs.pair_masses(D, hc_inputs.W_D20_F64)
+    tx, ty = on_gpu(x), on_gpu(y)
+    say("D=20 max-convolution: GPU, root in the last pass and separate")
+    za = hc.maxconv_pnorm(tx, ty, p)
+    zb = hc.maxconv_pnorm(tx, ty, p, separate_root=True)
+    torch.cuda.synchronize(DEV)
+    assert torch.equal(za.view(torch.int64), zb.view(torch.int64))
+    del zb
+    ks = sample_indices(D, 200, 3)
+    z_at = za[torch.from_numpy(ks.astype(np.int64)).to(DEV)].cpu().numpy()
+    ref = oracle.pnorm_at(x, y, p, ks)
+    tol, _ = pnorm_tolerance(x, y, p, D, ref, np.float64, ks=ks)
+    err = np.abs(z_at - ref)
+    say(f"D=20 max-convolution: max err/tol over {ks.size} samples = {np.max(err / tol):.3g}")
+    assert np.all(err <= tol)
+    del za
+    torch.cuda.empty_cache()
