@@ -238,3 +238,35 @@ def test_binding_rejects_bad_workspace_and_host_tensors():
     x = torch.ones(4, dtype=torch.float64)
     with pytest.raises(ValueError, match="HIP device"):
         hc.convolve(x, x)
+
+
+def _no_gpu():
+    try:
+        import torch
+        return not torch.cuda.is_available()
+    except Exception:
+        return True
+
+
+@pytest.mark.skipif(not _no_gpu(), reason="fake pointers must never reach a GPU")
+def test_validation_never_crashes_on_random_arguments():
+    """Random argument combinations (including out-of-range D, dtype and
+    batch, null, misaligned and overlapping pointers, short workspaces) return
+    a documented status code; on a host without a GPU even valid ones stop at
+    HC_ERR_NO_DEVICE, so nothing is ever launched."""
+    from hypothesis import given, settings, strategies as st
+
+    ptrs = st.sampled_from([0, FAKE, FAKE + 4, FAKE + 8, FAKE + (1 << 20), FAKE + (1 << 34), FAKE + (1 << 36) + 2])
+
+    @settings(max_examples=400, deadline=None)
+    @given(x=ptrs, y=ptrs, z=ptrs, D=st.integers(-3, 25), dtype=st.integers(-2, 4),
+           batch=st.integers(-2, 70000), ws=ptrs, wsb=st.sampled_from([0, 1, 16, 1 << 20, 1 << 40]))
+    def run(x, y, z, D, dtype, batch, ws, wsb):
+        rc = _abi.hc_convolve_batch(x, y, z, D, dtype, batch, ws, wsb, 0)
+        assert rc in (1, 2, 3, 4, 5, 6, 7), rc
+        rc = _abi.hc_maxconv_pnorm_batch(x, y, z, D, dtype, max(batch, 0) % 4, 2.0, 0, ws, wsb, 0)
+        assert rc in (1, 2, 3, 4, 5, 6, 7), rc
+        rc = _abi.hc_difference_batch(x, y, z, D, dtype, batch, ws, wsb, 0)
+        assert rc in (1, 2, 3, 4, 5, 6, 7), rc
+
+    run()
