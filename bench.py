@@ -444,8 +444,17 @@ def run_backward(args, torch, hc, steps=None, warmup=None):
     fwd_ms, _, fstats = time_steps(fwd, steps, warmup, torch)
     bwd_ms, _, bstats = time_steps(bwd, steps, warmup, torch)
     log(f"backward: fwd {fwd_ms:.3f} ms, bwd {bwd_ms:.3f} ms")
+    # the same backward with one weight vector shared by all pairs (grad_z
+    # with batch stride 0): the library computes its adjoint transform once
+    Wb = W[0].expand(B, 3 ** D)
+
+    def bwd_shared():
+        hc.convolve_backward(X, Y, Wb, workspace=wsb)
+
+    bwd_shared_ms, _, _ = time_steps(bwd_shared, steps, warmup, torch)
+    log(f"backward with one shared w: {bwd_shared_ms:.3f} ms")
     n_out = B * 3 ** D
-    del Z, wsf, wsb, W
+    del Z, wsf, wsb, W, Wb
     torch.cuda.empty_cache()
     return {
         "metric": METRIC, "value": round(n_out / ((fwd_ms + bwd_ms) / 1e3), 1), "unit": "output elems/s (fwd+bwd)",
@@ -454,6 +463,7 @@ def run_backward(args, torch, hc, steps=None, warmup=None):
         "config": {"workload": f"{B} pairs D={D} float64 masses, loss sum(w*z), w iid N(0,1) per pair",
                    "D": D, "global_batch": B, "parallelism": "single GPU"},
         "fwd_ms": round(fwd_ms, 4), "bwd_ms": round(bwd_ms, 4), "fwd_bwd_ms": round(fwd_ms + bwd_ms, 4),
+        "bwd_shared_w_ms": round(bwd_shared_ms, 4),
         "roofline": roofline(bstats, steps, "backward"),
         "kernels": kernel_table(fstats, steps) + kernel_table(bstats, steps),
     }

@@ -529,7 +529,11 @@ int run_backward(const Plan& P, const T* x, const T* y, const T* gz, uint64_t gz
         T* gyt = gxt + (uint64_t)batch * P.xt_elems;
         T* gxtmp = gyt + (uint64_t)batch * P.xt_elems;
         T* gytmp = gxtmp + (uint64_t)batch * g_e;
-        // 1. G^T on the outer axes, ascending; the first pass reads grad_z
+        // 1. G^T on the outer axes, ascending; the first pass reads grad_z.
+        // A broadcast grad_z (batch stride 0) gives every item the same W,
+        // computed once and read by all items.
+        const int w_items = gz_bs == 0 ? 1 : batch;
+        const uint64_t w_bs = gz_bs == 0 ? 0 : P.n3;
         const T* src = gz;
         uint64_t src_bs = gz_bs;
         for (int i = (int)P.inv.size() - 1; i >= 0; --i) {
@@ -537,7 +541,7 @@ int run_backward(const Plan& P, const T* x, const T* y, const T* gz, uint64_t gz
             const int m = ip.mR + ip.mW;
             const uint64_t L = pow3u(D - ip.a - m);
             const uint32_t n_hi = (uint32_t)pow3u(ip.a);
-            rc = launch_pass<T, true>(ip, src, W, src_bs, P.n3, L, n_hi, batch, cus, P.grid_per_cu, s);
+            rc = launch_pass<T, true>(ip, src, W, src_bs, P.n3, L, n_hi, w_items, cus, P.grid_per_cu, s);
             if (rc != HC_OK) return rc;
             src = W;
             src_bs = P.n3;
@@ -564,7 +568,7 @@ int run_backward(const Plan& P, const T* x, const T* y, const T* gz, uint64_t gz
             a += M;
         }
         // 3. fused inner adjoint: w_hat rows -> gx~, gy~ rows
-        rc = launch_fused_adj<T>(K, xt, yt, W, gx ? gxt : nullptr, gy ? gyt : nullptr, P.xt_elems, P.n3,
+        rc = launch_fused_adj<T>(K, xt, yt, W, gx ? gxt : nullptr, gy ? gyt : nullptr, P.xt_elems, w_bs,
                                  P.xt_elems, (uint32_t)pow3u(P.p), batch, cus, P.grid_per_cu, s);
         if (rc != HC_OK) return rc;
         // 4. F^T on the outer axes, descending groups (reverse of the forward)

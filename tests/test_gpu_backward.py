@@ -80,6 +80,27 @@ def test_backward_batch(broadcast):
         pins.assert_bitwise(gy[b].cpu().numpy(), ry, f"grad_y item {b}")
 
 
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_shared_weights_match_materialised_copies(dtype):
+    """With grad_z of batch stride 0 the library computes the adjoint of w
+    once for all items; the gradients equal those of B materialised copies of
+    w, bit for bit (D = 14: outer passes and the fused adjoint tile)."""
+    D, B = 14, 6
+    pairs = [hc_inputs.random_pair(D, dtype, seed=60 + b) for b in range(B)]
+    X = on_gpu(np.stack([p[0] for p in pairs]))
+    Y = on_gpu(np.stack([p[1] for p in pairs]))
+    w = on_gpu(np.random.default_rng([10, D]).standard_normal(3 ** D).astype(dtype))
+    gx1, gy1 = hc.convolve_backward(X, Y, w.expand(B, 3 ** D))
+    gx2, gy2 = hc.convolve_backward(X, Y, w.expand(B, 3 ** D).contiguous())
+    torch.cuda.synchronize(DEV)
+    iv = torch.int64 if np.dtype(dtype) == np.float64 else torch.int32
+    assert torch.equal(gx1.view(iv), gx2.view(iv))
+    assert torch.equal(gy1.view(iv), gy2.view(iv))
+    rx, ry = oracle.adjoint(pairs[3][0], pairs[3][1], w.cpu().numpy())
+    pins.assert_bitwise(gx1[3].cpu().numpy(), rx, "grad_x item 3, shared w")
+    pins.assert_bitwise(gy1[3].cpu().numpy(), ry, "grad_y item 3, shared w")
+
+
 def test_only_one_gradient_requested():
     D = 12
     x, y = hc_inputs.random_pair(D, np.float64, seed=50)
