@@ -140,7 +140,8 @@ size_t hc_backward_workspace_bytes(int D, int dtype, int batch);
  *   x, y          device, batch x 2^D (read only)
  *   grad_z        device, 3^D elements per batch item at stride
  *                 grad_z_stride elements; stride 0 broadcasts one w to every
- *                 item (read only)
+ *                 item, whose G^T transform is then computed once for all
+ *                 items (read only)
  *   grad_x/grad_y device, batch x 2^D (written); either may be NULL
  *   workspace     at least hc_backward_workspace_bytes(D, dtype, batch)
  * Supported dtypes: HC_F64, HC_F32 (HC_I64 returns HC_ERR_UNSUPPORTED).
