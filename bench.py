@@ -14,6 +14,7 @@ Workloads (inputs from hc_inputs, seeded and synthetic):
   all       (default) d20 as the headline value, plus batched, backward and
             apps measured after it and reported under "secondary"
   d20       one pair, D=20, float64 masses (3^20 outputs)
+  d20-f32   the same pair in float32
   d16-f64   one pair, D=16, float64 masses
   d16-i64   one pair, D=16, int64 values in [0, 15]
   d10       one pair, D=10, float64 masses
@@ -225,7 +226,8 @@ def cpu_baseline(x, y, z_gpu, D):
     for s in range(0, out.size, chunk):
         e = min(s + chunk, out.size)
         g = z_gpu[s:e].cpu().numpy()
-        if not np.array_equal(g.view(np.int64), out[s:e].view(np.int64)):
+        iv = np.int32 if g.dtype.itemsize == 4 else np.int64
+        if not np.array_equal(g.view(iv), out[s:e].view(iv)):
             equal = False
             break
     log(f"cpu baseline: {dt:.2f} s; GPU output bitwise equal: {equal}")
@@ -267,6 +269,11 @@ def run_single(args, torch, hc, D, dtype_name):
         x, y = hc_inputs.pair_ints(D, hc_inputs.W_D16)
         tdt = torch.int64
         desc = f"single pair D={D} int64, iid integers in [0,15] (seeded)"
+    elif dtype_name == "f32":
+        x, y = hc_inputs.pair_masses(D, hc_inputs.W_D20_F64)
+        x, y = x.astype(np.float32), y.astype(np.float32)
+        tdt = torch.float32
+        desc = f"single pair D={D} float32, iid U[0,1) normalised to sum 1 in float64, then rounded (seeded)"
     else:
         wl = {20: hc_inputs.W_D20_F64, 16: hc_inputs.W_D16, 10: hc_inputs.W_D10_F64}[D]
         x, y = hc_inputs.pair_masses(D, wl)
@@ -475,7 +482,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="all",
-                    choices=["all", "d20", "d16-f64", "d16-i64", "d10", "batched", "backward", "apps"])
+                    choices=["all", "d20", "d20-f32", "d16-f64", "d16-i64", "d10", "batched", "backward", "apps"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain copy kernel of known size before the workload (for counter passes)")
@@ -513,8 +520,9 @@ def main():
                                                "global_batch": 4096, "parallelism": "single GPU"},
                "batched": b}
     else:
-        D = {"all": 20, "d20": 20, "d16-f64": 16, "d16-i64": 16, "d10": 10}[args.workload]
-        res = run_single(args, torch, hc, D, "i64" if args.workload == "d16-i64" else "f64")
+        D = {"all": 20, "d20": 20, "d20-f32": 20, "d16-f64": 16, "d16-i64": 16, "d10": 10}[args.workload]
+        dt = {"d16-i64": "i64", "d20-f32": "f32"}.get(args.workload, "f64")
+        res = run_single(args, torch, hc, D, dt)
         if args.workload == "all":
             # the other parts of the metric, measured after the headline and
             # outside its timed region

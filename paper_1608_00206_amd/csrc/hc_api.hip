@@ -164,6 +164,19 @@ int max_fused_depth(int dtype)
     return dtype_size(dtype) == 4 ? 9 : 8;
 }
 
+// Default fused depth.  4-byte elements allow K = 9, but the K = 8 tile runs
+// at a higher occupancy and is faster, unless K = 9 saves a whole outer pass
+// or K = 8 would leave a last pass of 5 axes (4 register and 1 wave axes),
+// the slowest pass shape in float32.
+static int default_depth(int D, int dtype)
+{
+    const int kmax = max_fused_depth(dtype);
+    if (kmax != 9 || D < 9) return kmax;
+    const int p8 = D - 8, p9 = D - 9;
+    if ((p9 + 5) / 6 < (p8 + 5) / 6 || p8 % 6 == 5) return 9;
+    return 8;
+}
+
 Plan make_plan(int D, int dtype, const PlanOpts& o)
 {
     Plan P;
@@ -171,7 +184,7 @@ Plan make_plan(int D, int dtype, const PlanOpts& o)
     P.dtype = dtype;
     P.esize = dtype_size(dtype);
     const int kmax = max_fused_depth(dtype);
-    int K = o.fused_depth > 0 ? o.fused_depth : kmax;
+    int K = o.fused_depth > 0 ? o.fused_depth : default_depth(D, dtype);
     if (K > kmax) K = kmax;
     if (K > D) K = D;
     P.K = K;

@@ -9,7 +9,7 @@ configuration the benchmark times (default plans, tuned batched plans).
   D=20 float64   every output (3^20 = 3.49e9) bitwise against the canonical
                  method (the recursion on 16 host threads), compared in
                  chunks; sampled outputs within the bound of the definition
-  D=17, 19 float64, D=20 float32, D=18 int64
+  D=17, 19 float64, D=19, 20 float32, D=18 int64
                  every output bitwise against the recursion (the other
                  default plans at large D)
   batched        4096 pairs, D uniform in {6..14}, float64 and float32, tuned
@@ -119,12 +119,13 @@ def test_d20_f64_every_output_bitwise():
     torch.cuda.empty_cache()
 
 
-@pytest.mark.parametrize("D,dtype", [(17, np.float64), (19, np.float64), (20, np.float32), (18, np.int64)])
+@pytest.mark.parametrize("D,dtype", [(17, np.float64), (19, np.float64), (19, np.float32), (20, np.float32),
+                                     (18, np.int64)])
 def test_large_plans_every_output_bitwise(D, dtype):
-    """The default plans of the other large shapes (fused depth 9 and
-    different outer pass splits for float32, 5- and 6-axis pass pairs for
-    float64, int64 wrapping arithmetic), every output bitwise against the
-    recursion on 16 host threads."""
+    """The default plans of the other large shapes (float32 with fused depth
+    9 at D = 19 and 8 at D = 20, 5- and 6-axis pass pairs for float64, int64
+    wrapping arithmetic), every output bitwise against the recursion on 16
+    host threads."""
     n3 = 3 ** D
     if np.dtype(dtype) == np.int64:
         x, y = hc_inputs.pair_ints(D, hc_inputs.W_D16)
