@@ -166,8 +166,8 @@ int max_fused_depth(int dtype)
 
 // Default fused depth.  4-byte elements allow K = 9, but the K = 8 tile runs
 // at a higher occupancy and is faster, unless K = 9 saves a whole outer pass
-// or K = 8 would leave a last pass of 5 axes (4 register and 1 wave axes),
-// the slowest pass shape in float32.
+// or K = 8 would leave a last pass of 5 axes (measured slower than the K = 9
+// plan at D = 13; even at D = 19).
 static int default_depth(int D, int dtype)
 {
     const int kmax = max_fused_depth(dtype);
@@ -214,6 +214,11 @@ Plan make_plan(int D, int dtype, const PlanOpts& o)
         ip.a = a;
         ip.mR = m < reg ? m : reg;
         ip.mW = m - ip.mR;
+        // five axes run faster as 3 register + 2 wave axes than as 4 + 1
+        if (m == 5 && ip.mR == 4) {
+            ip.mR = 3;
+            ip.mW = 2;
+        }
         P.inv.push_back(ip);
         top = a;
     }

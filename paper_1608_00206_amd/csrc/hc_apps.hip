@@ -284,25 +284,31 @@ struct RootEpilogue {
     }
 };
 
-// LastPass::launch for the root: the streamed-thirds passes (4 register and
-// 1 or 2 wave axes) have an epilogue kernel; other shapes decline.
+// LastPass::launch for the root: passes of 4 register and 1 or 2 wave axes
+// and of 3 register and 2 wave axes (the shapes of the last pass of default
+// plans from D = 13 on) have an epilogue kernel; other shapes decline.
 template <typename T, int MODE>
 static int launch_root_pass(const LastPass& self, const InvPass& ip, void* z, BMap z_map, uint64_t L,
                             uint32_t n_hi, int batch, int cus, hipStream_t s)
 {
-    if (ip.mR != 4 || (ip.mW != 1 && ip.mW != 2)) return HC_ERR_UNSUPPORTED;
-    const RootEpilogue<T, MODE>& epi = *static_cast<const RootEpilogue<T, MODE>*>(self.ctx);
+    using EP = RootEpilogue<T, MODE>;
+    const bool ok = (ip.mR == 4 && (ip.mW == 1 || ip.mW == 2)) || (ip.mR == 3 && ip.mW == 2);
+    if (!ok) return HC_ERR_UNSUPPORTED;
+    const EP& epi = *static_cast<const EP*>(self.ctx);
     const uint32_t tiles_per_hi = (uint32_t)((L + 63) / 64);
     const uint64_t n_tiles = (uint64_t)tiles_per_hi * n_hi;
     const dim3 grid(tile_grid(n_tiles, cus, 0), batch, 1);
-    const int TM = (int)pow3u(4 + ip.mW);
-    LaunchScope scope(s, 2.0 * batch * n_hi * L * TM * sizeof(T), "inv_pass_root<%s,4+%d>", tname<T>(), ip.mW);
-    if (ip.mW == 2)
-        k_inv_pass_epi<T, 2, RootEpilogue<T, MODE>><<<grid, 64 * 9, 0, s>>>((T*)z, z_map, L, tiles_per_hi,
-                                                                           (uint32_t)n_tiles, epi);
+    const int TM = (int)pow3u(ip.mR + ip.mW);
+    LaunchScope scope(s, 2.0 * batch * n_hi * L * TM * sizeof(T), "inv_pass_root<%s,%d+%d>", tname<T>(), ip.mR,
+                      ip.mW);
+    T* zt = static_cast<T*>(z);
+    const uint32_t nt = (uint32_t)n_tiles;
+    if (ip.mR == 4 && ip.mW == 2)
+        k_inv_pass_epi<T, 4, 2, EP><<<grid, 64 * 9, 0, s>>>(zt, z_map, L, tiles_per_hi, nt, epi);
+    else if (ip.mR == 4)
+        k_inv_pass_epi<T, 4, 1, EP><<<grid, 64 * 3, 0, s>>>(zt, z_map, L, tiles_per_hi, nt, epi);
     else
-        k_inv_pass_epi<T, 1, RootEpilogue<T, MODE>><<<grid, 64 * 3, 0, s>>>((T*)z, z_map, L, tiles_per_hi,
-                                                                           (uint32_t)n_tiles, epi);
+        k_inv_pass_epi<T, 3, 2, EP><<<grid, 64 * 9, 0, s>>>(zt, z_map, L, tiles_per_hi, nt, epi);
     return HC_OK;
 }
 

@@ -250,6 +250,16 @@ __global__ __launch_bounds__(NT) void k_fused_inner(const T* __restrict__ xt, co
 // ends at column L: lanes past L load zeros and their stores are dropped, and
 // a wave whose 64 columns all lie past L does nothing.
 // =========================================================================
+// Epilogue of a final inverse pass: NoEpilogue stores the entries the map
+// changes, as above.  An epilogue with ALL = true maps every entry of the
+// tile through apply() and stores them all (used to fuse an elementwise step
+// that follows the convolution into its last pass).
+struct NoEpilogue {
+    static constexpr bool ALL = false;
+    template <typename T>
+    __device__ __forceinline__ T apply(T v) const { return v; }
+};
+
 template <int mR, int mW, int CW>
 struct PassCfg {
     static_assert(mW == 0 || CW == 1, "several column groups only without the wave part");
@@ -271,8 +281,9 @@ struct PassCfg {
 // mW > 0.  With a wave part every wave is active (the tile's first column
 // j * 64 is below L); without one, a wave whose 64 columns all lie past L
 // skips its work.
-template <typename T, int mR, int mW, int CW, bool ADJ, bool IN_PLACE>
-__device__ __forceinline__ void inv_tile(const T* src, T* dst, uint64_t L, uint32_t hi, uint32_t j, int wave, T* S)
+template <typename T, int mR, int mW, int CW, bool ADJ, bool IN_PLACE, class E = NoEpilogue>
+__device__ __forceinline__ void inv_tile(const T* src, T* dst, uint64_t L, uint32_t hi, uint32_t j, int wave, T* S,
+                                         const E& epi = E{})
 {
     using P = PassCfg<mR, mW, CW>;
     constexpr int tR = P::tR, tW = P::tW, TM = tR * tW;
@@ -305,7 +316,8 @@ __device__ __forceinline__ void inv_tile(const T* src, T* dst, uint64_t L, uint3
 #pragma unroll
             for (int gR = 0; gR < tR; ++gR) {
                 const bool changed = ADJ ? !all_digits_one(gR, mR) : has_digit_one(gR, mR);
-                if (changed || !IN_PLACE) buf_store<T>(row_rsrc(wp, seg_bytes), col_off, v[gR]);
+                if constexpr (E::ALL) buf_store<T>(row_rsrc(wp, seg_bytes), col_off, epi.apply(v[gR]));
+                else if (changed || !IN_PLACE) buf_store<T>(row_rsrc(wp, seg_bytes), col_off, v[gR]);
                 wp += row_bytes;
             }
         }
@@ -347,7 +359,8 @@ __device__ __forceinline__ void inv_tile(const T* src, T* dst, uint64_t L, uint3
                     for (int gW = 0; gW < tW; ++gW) {
                         const bool changed = ADJ ? !(r_flag && all_digits_one(gW, mW))
                                                  : (r_flag || has_digit_one(gW, mW));
-                        if (changed || !IN_PLACE) buf_store<T>(row_rsrc(wp, seg_bytes), col_off, u[gW]);
+                        if constexpr (E::ALL) buf_store<T>(row_rsrc(wp, seg_bytes), col_off, epi.apply(u[gW]));
+                        else if (changed || !IN_PLACE) buf_store<T>(row_rsrc(wp, seg_bytes), col_off, u[gW]);
                         wp += step;
                     }
                 }
@@ -355,16 +368,6 @@ __device__ __forceinline__ void inv_tile(const T* src, T* dst, uint64_t L, uint3
         }
     }
 }
-
-// Epilogue of a final inverse pass: NoEpilogue stores the entries the map
-// changes, as above.  An epilogue with ALL = true maps every entry of the
-// tile through apply() and stores them all (used to fuse an elementwise step
-// that follows the convolution into its last pass).
-struct NoEpilogue {
-    static constexpr bool ALL = false;
-    template <typename T>
-    __device__ __forceinline__ T apply(T v) const { return v; }
-};
 
 // One tile of an inverse pass with mR = 4 and a wave part (CW = 1, every wave
 // active).  The 81 register values of a lane would not fit the register budget
@@ -551,23 +554,32 @@ __global__ __launch_bounds__(64 * pow3c(mW) * CW) void k_inv_pass(const T* src, 
     }
 }
 
-// The last inverse pass of a forward run with an epilogue: the in-place
-// streamed-thirds tile (mR = 4, 0 < mW), every entry mapped through
-// epi.bind(item).apply() and stored.  One tile per workgroup.
-template <typename T, int mW, class EP>
+// The last inverse pass of a forward run with an epilogue: in place, every
+// entry mapped through epi.bind(item).apply() and stored.  Launched like
+// k_inv_pass with the same tile counts (one tile per workgroup for the
+// streamed-thirds tile).
+template <typename T, int mR, int mW, class EP>
 __global__ __launch_bounds__(64 * pow3c(mW)) void k_inv_pass_epi(T* z, BMap z_map, uint64_t L,
                                                                  uint32_t tiles_per_hi, uint32_t n_tiles, EP epi)
 {
-    using P = PassCfg<4, mW, 1>;
-    static_assert(P::THIRDS, "epilogues run on the streamed-thirds tile");
+    using P = PassCfg<mR, mW, 1>;
+    static_assert(mW > 0, "epilogue passes have a wave part");
     __shared__ T S[P::LDS];
     z += z_map.at(blockIdx.y);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const TileWalk walk = xcd_tile_walk(n_tiles);
-    if (walk.first < walk.end) {
-        const uint32_t hi = walk.first / tiles_per_hi;
-        const auto e = epi.bind(blockIdx.y);
-        inv_tile_r4<T, mW, false, true>(z, z, L, hi, walk.first - hi * tiles_per_hi, wave, S, e);
+    const auto e = epi.bind(blockIdx.y);
+    if constexpr (P::THIRDS) {
+        if (walk.first < walk.end) {
+            const uint32_t hi = walk.first / tiles_per_hi;
+            inv_tile_r4<T, mW, false, true>(z, z, L, hi, walk.first - hi * tiles_per_hi, wave, S, e);
+        }
+    } else {
+        for (uint32_t t = walk.first; t < walk.end; t += walk.step) {
+            const uint32_t hi = t / tiles_per_hi;
+            lds_barrier();
+            inv_tile<T, mR, mW, 1, false, true>(z, z, L, hi, t - hi * tiles_per_hi, wave, S, e);
+        }
     }
 }
 

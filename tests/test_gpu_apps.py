@@ -293,11 +293,12 @@ def _kernel_names(fn):
                                            (14, np.float32, True), (15, np.float32, True)])
 @pytest.mark.parametrize("p", [1.0, 32.0, 7.5])
 def test_maxconv_root_in_last_pass_matches_separate_root(D, dtype, fused, p):
-    """Where the convolution's last inverse pass is a streamed-thirds pass (4
-    register and 1 or 2 wave axes) the root runs as its epilogue; the bits
-    equal those of the separate root kernel, for every root form, with and
-    without rounding, over a batch of 3 (per-item scales).  Other last
-    passes (D=15 float64: one axis) fall back to the separate kernel."""
+    """Where the convolution's last inverse pass has a wave part (D=13
+    float64: 3+2 axes; D=14 float64, D=14 and 15 float32: 4+2) the root runs
+    as its epilogue; the bits equal those of the separate root kernel, for
+    every root form, with and without rounding, over a batch of 3 (per-item
+    scales).  Other last passes (D=15 float64: one axis) fall back to the
+    separate kernel."""
     B = 3
     pairs = [hc_inputs.random_pair(D, dtype, 30 + b) for b in range(B)]
     X = on_gpu(np.stack([a for a, _ in pairs]))
