@@ -214,10 +214,11 @@ Plan make_plan(int D, int dtype, const PlanOpts& o)
         ip.a = a;
         ip.mR = m < reg ? m : reg;
         ip.mW = m - ip.mR;
-        // five axes run faster as 3 register + 2 wave axes than as 4 + 1
-        if (m == 5 && ip.mR == 4) {
+        // four and five axes run faster as 3 register axes plus 1 or 2 wave
+        // axes than as 4 + 0 and 4 + 1
+        if ((m == 4 || m == 5) && ip.mR == 4) {
             ip.mR = 3;
-            ip.mW = 2;
+            ip.mW = m - 3;
         }
         P.inv.push_back(ip);
         top = a;

@@ -284,15 +284,15 @@ struct RootEpilogue {
     }
 };
 
-// LastPass::launch for the root: passes of 4 register and 1 or 2 wave axes
-// and of 3 register and 2 wave axes (the shapes of the last pass of default
-// plans from D = 13 on) have an epilogue kernel; other shapes decline.
+// LastPass::launch for the root: passes of 3 or 4 register axes and 1 or 2
+// wave axes (the last pass of default plans whose last group has 4 to 6
+// axes) have an epilogue kernel; other shapes decline.
 template <typename T, int MODE>
 static int launch_root_pass(const LastPass& self, const InvPass& ip, void* z, BMap z_map, uint64_t L,
                             uint32_t n_hi, int batch, int cus, hipStream_t s)
 {
     using EP = RootEpilogue<T, MODE>;
-    const bool ok = (ip.mR == 4 && (ip.mW == 1 || ip.mW == 2)) || (ip.mR == 3 && ip.mW == 2);
+    const bool ok = (ip.mR == 3 || ip.mR == 4) && (ip.mW == 1 || ip.mW == 2);
     if (!ok) return HC_ERR_UNSUPPORTED;
     const EP& epi = *static_cast<const EP*>(self.ctx);
     const uint32_t tiles_per_hi = (uint32_t)((L + 63) / 64);
@@ -307,8 +307,10 @@ static int launch_root_pass(const LastPass& self, const InvPass& ip, void* z, BM
         k_inv_pass_epi<T, 4, 2, EP><<<grid, 64 * 9, 0, s>>>(zt, z_map, L, tiles_per_hi, nt, epi);
     else if (ip.mR == 4)
         k_inv_pass_epi<T, 4, 1, EP><<<grid, 64 * 3, 0, s>>>(zt, z_map, L, tiles_per_hi, nt, epi);
-    else
+    else if (ip.mW == 2)
         k_inv_pass_epi<T, 3, 2, EP><<<grid, 64 * 9, 0, s>>>(zt, z_map, L, tiles_per_hi, nt, epi);
+    else
+        k_inv_pass_epi<T, 3, 1, EP><<<grid, 64 * 3, 0, s>>>(zt, z_map, L, tiles_per_hi, nt, epi);
     return HC_OK;
 }
 

@@ -289,12 +289,13 @@ def _kernel_names(fn):
     return out, [st[0] for st in hc._abi.hc_profile_collect()]
 
 
-@pytest.mark.parametrize("D,dtype,fused", [(13, np.float64, True), (14, np.float64, True), (15, np.float64, False),
-                                           (14, np.float32, True), (15, np.float32, True)])
+@pytest.mark.parametrize("D,dtype,fused", [(12, np.float64, True), (13, np.float64, True), (14, np.float64, True),
+                                           (15, np.float64, False), (14, np.float32, True), (15, np.float32, True)])
 @pytest.mark.parametrize("p", [1.0, 32.0, 7.5])
 def test_maxconv_root_in_last_pass_matches_separate_root(D, dtype, fused, p):
-    """Where the convolution's last inverse pass has a wave part (D=13
-    float64: 3+2 axes; D=14 float64, D=14 and 15 float32: 4+2) the root runs
+    """Where the convolution's last inverse pass has a wave part (D=12
+    float64: 3+1 axes; D=13 float64: 3+2; D=14 float64, D=14 and 15
+    float32: 4+2) the root runs
     as its epilogue; the bits equal those of the separate root kernel, for
     every root form, with and without rounding, over a batch of 3 (per-item
     scales).  Other last passes (D=15 float64: one axis) fall back to the
