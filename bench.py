@@ -126,7 +126,10 @@ def write_traffic(args) -> None:
         raise SystemExit("--write-traffic takes WORKLOAD FETCH_CSV WRITE_CSV triples")
 
     def per_kernel(path, counter):
-        acc, cal = {}, []
+        # dispatches of one kernel whose grid is under half the largest grid
+        # of that kernel in the run (the shared-weight backward's single-item
+        # passes) are different launches from the timed ones and are left out
+        rows, cal = {}, []
         with open(path, newline="") as f:
             for row in csv.DictReader(f):
                 if row.get("Counter_Name") != counter:
@@ -137,9 +140,13 @@ def write_traffic(args) -> None:
                     continue
                 pn = profiler_name(name)
                 if pn is not None:
-                    acc.setdefault(pn, []).append(val)
+                    rows.setdefault(pn, []).append((int(row["Grid_Size"]), val))
         if len(cal) != 1:
             raise SystemExit(f"{path}: expected one calibration copy dispatch, found {len(cal)}")
+        acc = {}
+        for pn, lst in rows.items():
+            top = max(g for g, _ in lst)
+            acc[pn] = [v for g, v in lst if 2 * g >= top]
         return acc, cal[0]
 
     workloads, fcals, wcals = {}, [], []
