@@ -39,13 +39,13 @@ CFLAGS = ["-O2", "-std=c11", "-Wall", "-Wextra", "-ffp-contract=off", "-fno-fast
 _lib = None
 
 
-def build() -> str:
+def build(source: str = SOURCES[0], target: str = LIB_PATH, extra_flags=()) -> str:
     """Compile the oracle shared library with gcc (always recompiles)."""
-    tmp = LIB_PATH + ".tmp"
-    cmd = ["gcc", *CFLAGS, "-o", tmp, SOURCES[0], "-lm"]
+    tmp = target + ".tmp"
+    cmd = ["gcc", *CFLAGS, *extra_flags, "-o", tmp, source, "-lm"]
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB_PATH)
-    return LIB_PATH
+    os.replace(tmp, target)
+    return target
 
 
 def _load():
@@ -54,7 +54,14 @@ def _load():
         return _lib
     if not os.path.exists(LIB_PATH):
         build()
-    lib = ctypes.CDLL(LIB_PATH)
+    _lib = configure(ctypes.CDLL(LIB_PATH))
+    return _lib
+
+
+def configure(lib):
+    """Declare the argument and result types of the oracle's exports on a
+    loaded library (the oracle itself, or a copy built from edited sources
+    by the tests that plant mistakes in it)."""
     P = ctypes.c_void_p
     I = ctypes.c_int
     I64 = ctypes.c_int64
@@ -90,7 +97,6 @@ def _load():
     lib.hco_bound_at_f64.restype = I
     lib.hco_adjoint_bound_f64.argtypes = [P, P, P, P, P, I]
     lib.hco_adjoint_bound_f64.restype = I
-    _lib = lib
     return lib
 
 

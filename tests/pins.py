@@ -250,3 +250,122 @@ def pin_matches_recursion(impl, dtype, D, recursion, seed=0):
     y = g.random(1 << D)
     x, y = (x / x.sum()).astype(dtype), (y / y.sum()).astype(dtype)
     assert_bitwise(impl(x, y), recursion(x, y), f"matches recursion D={D}")
+
+
+# ------------------------------------------------------------- rounding bounds
+# The bound B = |G|(F|x| . F|y|) and the adjoint bounds are tensor products of
+# per-axis factors whenever the inputs are: for x = (x) over axes of
+# (a_d, b_d) and y of (c_d, e_d), the forward map gives (|a|, |a|+|b|, |b|),
+# the product multiplies per axis, and |G| sends (p0, p1, p2) to
+# (p0, p0 + p1 + p2, p2).  These closed forms fix B from both sides: a
+# dropped term, a wrong index or a scaled result changes them.
+
+def rank1(factors) -> np.ndarray:
+    """Outer product over the axes, axis 0 (first factor) most significant."""
+    out = np.ones(1)
+    for f in factors:
+        out = np.kron(out, np.asarray(f, dtype=np.float64))
+    return out
+
+
+def rank1_factors(D: int, seed: int, width: int = 2, lo: int = 1, hi: int = 4):
+    """Per-axis factors of small signed integers (|v| in [lo, hi))."""
+    g = np.random.default_rng([61, D, seed, width])
+    mag = g.integers(lo, hi, (D, width)).astype(np.float64)
+    sign = np.where(g.random((D, width)) < 0.5, -1.0, 1.0)
+    return list(mag * sign)
+
+
+def bound_closed_form(fx, fy) -> np.ndarray:
+    per_axis = []
+    for (a, b), (c, e) in zip(fx, fy):
+        a, b, c, e = abs(a), abs(b), abs(c), abs(e)
+        p0, p1, p2 = a * c, (a + b) * (c + e), b * e
+        per_axis.append((p0, p0 + p1 + p2, p2))
+    return rank1(per_axis)
+
+
+def bound_closed_form_at(fx, fy, ks) -> np.ndarray:
+    """The same closed form at single output indices (digits of k, axis 0
+    most significant), as exact products in Python integers or floats."""
+    D = len(fx)
+    out = []
+    for k in ks:
+        digits = ternary_digits(int(k), D)
+        v = 1.0
+        for d, dig in enumerate(digits):
+            a, b = (abs(t) for t in fx[d])
+            c, e = (abs(t) for t in fy[d])
+            p0, p1, p2 = a * c, (a + b) * (c + e), b * e
+            v *= (p0, p0 + p1 + p2, p2)[dig]
+        out.append(v)
+    return np.array(out)
+
+
+def adjoint_bound_closed_form(fw, fo):
+    """Bx for w = (x) of (w0, w1, w2)_d and the other operand (x) of (c, e)_d:
+    |G^T| gives (|w0|+|w1|, |w1|, |w2|+|w1|), F|.| gives (|c|, |c|+|e|, |e|),
+    the product multiplies per axis, |F^T| gives (g0 + g1, g1 + g2)."""
+    per_axis = []
+    for (w0, w1, w2), (c, e) in zip(fw, fo):
+        w0, w1, w2, c, e = abs(w0), abs(w1), abs(w2), abs(c), abs(e)
+        g0, g1, g2 = (w0 + w1) * c, w1 * (c + e), (w2 + w1) * e
+        per_axis.append((g0 + g1, g1 + g2))
+    return rank1(per_axis)
+
+
+def pin_bound_all_ones(bound_fn, D):
+    """x = y = 1: B[k] = 6^(number of digits of k equal to 1), exactly."""
+    x = np.ones(1 << D)
+    expect = 6.0 ** ones_count_ternary(3 ** D)
+    assert_bitwise(bound_fn(x, x.copy()), expect, f"bound all-ones D={D}")
+
+
+def pin_bound_rank1(bound_fn, D, seed=0):
+    """Outer-product inputs with distinct small integers per axis: every
+    intermediate is an integer below 2^53 for D <= 8, so B equals its closed
+    form exactly."""
+    fx, fy = rank1_factors(D, seed), rank1_factors(D, seed + 1000)
+    expect = bound_closed_form(fx, fy)
+    assert expect.max() < 2.0 ** 53
+    assert_bitwise(bound_fn(rank1(fx), rank1(fy)), expect, f"bound rank-1 D={D}")
+
+
+def pin_bound_at_closed_forms(bound_at_fn, D, n=64, seed=0):
+    """The per-index bound at large D: all-ones inputs give 6^s exactly (s
+    digits equal to 1); outer-product inputs give the per-axis product within
+    the rounding of D multiplications."""
+    g = np.random.default_rng([67, D, seed])
+    ks = g.integers(0, 3 ** D, 4 * n, dtype=np.uint64)
+    ks = np.array([k for k in ks if sum(d == 1 for d in ternary_digits(int(k), D)) <= 14][:n]
+                  + [0, 3 ** D - 1, (3 ** min(D, 14) - 1) // 2], dtype=np.uint64)
+    ones = np.ones(1 << D)
+    s = np.array([sum(d == 1 for d in ternary_digits(int(k), D)) for k in ks])
+    assert_bitwise(bound_at_fn(ones, ones.copy(), ks), 6.0 ** s, f"bound_at all-ones D={D}")
+    fx, fy = rank1_factors(D, seed), rank1_factors(D, seed + 1000)
+    got = bound_at_fn(rank1(fx), rank1(fy), ks)
+    expect = bound_closed_form_at(fx, fy, ks)
+    assert np.all(np.abs(got - expect) <= 4 * D * 2.0 ** -53 * expect), \
+        f"bound_at rank-1 D={D}: max rel {np.max(np.abs(got - expect) / expect):.3g}"
+
+
+def pin_adjoint_bound_closed_forms(adjoint_bound_fn, D, seed=0):
+    """x = y = w = 1 gives Bx = By = 4^D exactly; outer-product x, y, w give
+    the per-axis products (x's factors enter By, y's enter Bx)."""
+    ones2, ones3 = np.ones(1 << D), np.ones(3 ** D)
+    bx, by = adjoint_bound_fn(ones2, ones2.copy(), ones3)
+    assert np.all(bx == 4.0 ** D) and np.all(by == 4.0 ** D), f"adjoint bound all-ones D={D}"
+    fx, fy = rank1_factors(D, seed), rank1_factors(D, seed + 1000)
+    fw = rank1_factors(D, seed + 2000, width=3)
+    bx, by = adjoint_bound_fn(rank1(fx), rank1(fy), rank1(fw))
+    ex, ey = adjoint_bound_closed_form(fw, fy), adjoint_bound_closed_form(fw, fx)
+    tol = 6 * D * 2.0 ** -53
+    assert np.all(np.abs(bx - ex) <= tol * ex), f"adjoint bound x rank-1 D={D}"
+    assert np.all(np.abs(by - ey) <= tol * ey), f"adjoint bound y rank-1 D={D}"
+
+
+def error_ratio_band(ratio: float, D: int, lo: float = 0.05) -> None:
+    """The largest measured |err| / (u B) lies between lo and 4D + 2: above
+    the certified factor the bound is violated; far below any measured value
+    (0.5 to 1.5 on the workloads' masses) the bound would be inflated."""
+    assert lo <= ratio <= 4 * D + 2, f"max |err|/(u B) = {ratio:.3g} outside [{lo}, {4 * D + 2}]"

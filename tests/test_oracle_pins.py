@@ -279,3 +279,43 @@ def test_int64_wrapping_intermediate_written_out():
     y = np.array([1, 0], dtype=np.int64)
     for name in EXACT_IMPLS:
         assert IMPLS[name](x, y).tolist() == [1 << 62, 1 << 62, 0], name
+
+
+# ------------------------------------------------- the rounding bounds, pinned
+# Closed forms fix B from above as well as below (a bound inflated by any
+# factor fails them); tests/test_oracle_bound_mutants.py shows that planted
+# mistakes in the bound code are caught.
+
+@pytest.mark.parametrize("D", [0, 1, 3, 6, 10, 12])
+def test_bound_all_ones_closed_form(D):
+    pins.pin_bound_all_ones(oracle.bound, D)
+
+
+@pytest.mark.parametrize("D", [1, 2, 5, 8])
+def test_bound_rank1_closed_form(D):
+    pins.pin_bound_rank1(oracle.bound, D)
+
+
+@pytest.mark.parametrize("D", [12, 16, 20, 21])
+def test_bound_at_closed_forms_large_d(D):
+    pins.pin_bound_at_closed_forms(oracle.bound_at, D)
+
+
+@pytest.mark.parametrize("D", [0, 1, 4, 7, 10])
+def test_adjoint_bound_closed_forms(D):
+    pins.pin_adjoint_bound_closed_forms(oracle.adjoint_bound, D)
+
+
+@pytest.mark.parametrize("D", [8, 10, 12])
+def test_mass_error_ratio_in_band(D):
+    """On the workloads' normalised masses the largest |err|/(u B) against
+    the compensated definition sum lies in the band the full-size GPU checks
+    assert (it measures 0.5 to 1.5 there)."""
+    x, y = hc_inputs.pair_masses(D, hc_inputs.W_D16)
+    z = oracle.canonical(x, y)
+    ks = np.arange(3 ** D, dtype=np.uint64) if D <= 10 else \
+        np.random.default_rng([71, D]).integers(0, 3 ** D, 4096, dtype=np.uint64)
+    ref = oracle.direct_at(x, y, ks)
+    B = oracle.bound_at(x, y, ks) if D > 10 else oracle.bound(x, y)
+    r = float(np.max(np.abs(z[ks.astype(np.int64)] - ref) / B) / 2.0 ** -53)
+    pins.error_ratio_band(r, D)
