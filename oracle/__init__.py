@@ -31,7 +31,8 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liboracle.so")
-SOURCES = [os.path.join(_HERE, "hc_oracle.c"), os.path.join(_HERE, "hc_oracle_impl.h")]
+SOURCES = [os.path.join(_HERE, "hc_oracle.c"), os.path.join(_HERE, "hc_oracle_impl.h"),
+           os.path.join(_HERE, "hc_oracle_sum3.h")]
 
 CFLAGS = ["-O2", "-std=c11", "-Wall", "-Wextra", "-ffp-contract=off", "-fno-fast-math",
           "-fopenmp", "-fPIC", "-shared"]
@@ -71,7 +72,9 @@ def configure(lib):
                            ("hco_recursive_", [P, P, P, I, I]),
                            ("hco_adjoint_", [P, P, P, P, P, I]),
                            ("hco_carryfree_naive_", [P, P, ctypes.c_uint64, P]),
-                           ("hco_difference_naive_", [P, P, P, I])):
+                           ("hco_difference_naive_", [P, P, P, I]),
+                           ("hco_sum3_naive_", [P, P, P, P, I]),
+                           ("hco_sum3_canonical_", [P, P, P, P, I])):
             fn = getattr(lib, name + sfx)
             fn.argtypes = args
             fn.restype = I
@@ -97,6 +100,10 @@ def configure(lib):
     lib.hco_bound_at_f64.restype = I
     lib.hco_adjoint_bound_f64.argtypes = [P, P, P, P, P, I]
     lib.hco_adjoint_bound_f64.restype = I
+    lib.hco_sum3_direct_at_f64.argtypes = [P, P, P, I, P, I64, P]
+    lib.hco_sum3_direct_at_f64.restype = None
+    lib.hco_sum3_bound_f64.argtypes = [P, P, P, P, I]
+    lib.hco_sum3_bound_f64.restype = I
     return lib
 
 
@@ -299,6 +306,59 @@ def adjoint_bound(x, y, w):
     by = np.empty(1 << D, dtype=np.float64)
     _load().hco_adjoint_bound_f64(_ptr(x), _ptr(y), _ptr(w), _ptr(bx), _ptr(by), D)
     return bx, by
+
+
+def _triple(x1, x2, x3):
+    x1, x2, x3 = _vec(x1), _vec(x2), _vec(x3)
+    if not (x1.dtype == x2.dtype == x3.dtype and x1.size == x2.size == x3.size):
+        raise ValueError("x1, x2 and x3 must have the same dtype and size")
+    return x1, x2, x3, dim_of(x1), _SFX[x1.dtype]
+
+
+def sum3_naive(x1, x2, x3) -> np.ndarray:
+    """Distribution of X1 + X2 + X3 (three hypercubes, 4^D outputs, base-4
+    digit = sum of the three bits) by its definition, every triple of
+    entries (D <= 12)."""
+    x1, x2, x3, D, sfx = _triple(x1, x2, x3)
+    z = np.empty(4 ** D, dtype=x1.dtype)
+    rc = getattr(_load(), "hco_sum3_naive_" + sfx)(_ptr(x1), _ptr(x2), _ptr(x3), _ptr(z), D)
+    if rc:
+        raise RuntimeError(f"hco_sum3_naive_{sfx} failed ({rc})")
+    return z
+
+
+def sum3_canonical(x1, x2, x3) -> np.ndarray:
+    """The same distribution by the per-axis method for three operands:
+    forward (a0, a0 + a1, a0 - a1, a1) on axes 0..D-1, the product
+    (x1^ x2^) x3^, inverse from the values at 0, 1, -1 and infinity on axes
+    D-1..0 (D <= 14)."""
+    x1, x2, x3, D, sfx = _triple(x1, x2, x3)
+    z = np.empty(4 ** D, dtype=x1.dtype)
+    rc = getattr(_load(), "hco_sum3_canonical_" + sfx)(_ptr(x1), _ptr(x2), _ptr(x3), _ptr(z), D)
+    if rc:
+        raise RuntimeError(f"hco_sum3_canonical_{sfx} failed ({rc})")
+    return z
+
+
+def sum3_direct_at(x1, x2, x3, ks) -> np.ndarray:
+    """Definition of the three-operand distribution at chosen indices,
+    compensated long double sums (float64 data)."""
+    x1, x2, x3, D, _ = _triple(*(np.asarray(v, dtype=np.float64) for v in (x1, x2, x3)))
+    ks = np.ascontiguousarray(ks, dtype=np.uint64).reshape(-1)
+    if ks.size and int(ks.max()) >= 4 ** D:
+        raise ValueError("output index out of range")
+    out = np.empty(ks.size, dtype=np.float64)
+    _load().hco_sum3_direct_at_f64(_ptr(x1), _ptr(x2), _ptr(x3), D, _ptr(ks), ks.size, _ptr(out))
+    return out
+
+
+def sum3_bound(x1, x2, x3) -> np.ndarray:
+    """B with |sum3_canonical - exact| <= (5D + 2) u B."""
+    x1, x2, x3, D, _ = _triple(*(np.asarray(v, dtype=np.float64) for v in (x1, x2, x3)))
+    b = np.empty(4 ** D, dtype=np.float64)
+    if _load().hco_sum3_bound_f64(_ptr(x1), _ptr(x2), _ptr(x3), _ptr(b), D):
+        raise ValueError("sum3_bound: D out of range")
+    return b
 
 
 def unit_roundoff(dtype) -> float:

@@ -18,6 +18,9 @@
  *   hco_adjoint_*    transposed maps (gradient of sum(w * z))
  *   hco_carryfree_naive_*   carry-free 1-D convolution by its definition
  *   hco_difference_naive_*  distribution of X - Y by its definition
+ *   hco_sum3_naive_*, hco_sum3_canonical_*  distribution of X1 + X2 + X3
+ *                    by its definition and by the per-axis method extended
+ *                    to three operands (hc_oracle_sum3.h)
  * plus fp64/long double helpers for pins: the max-convolution and its p-norm
  * estimate at single indices, the ternary index map, the direct
  * per-element definition sum, the direct correlation gradient and the
@@ -65,21 +68,30 @@ uint64_t hco_tern(uint64_t i)
 
 #define ELEM double
 #define SFX f64
+#define HCO_HALF(v) ((v) * 0.5)
 #include "hc_oracle_impl.h"
+#include "hc_oracle_sum3.h"
 #undef ELEM
 #undef SFX
+#undef HCO_HALF
 
 #define ELEM float
 #define SFX f32
+#define HCO_HALF(v) ((v) * 0.5f)
 #include "hc_oracle_impl.h"
+#include "hc_oracle_sum3.h"
 #undef ELEM
 #undef SFX
+#undef HCO_HALF
 
 #define ELEM uint64_t
 #define SFX i64
+#define HCO_HALF(v) ((uint64_t)((int64_t)(v) / 2))
 #include "hc_oracle_impl.h"
+#include "hc_oracle_sum3.h"
 #undef ELEM
 #undef SFX
+#undef HCO_HALF
 
 /* Neumaier-compensated accumulation in long double. */
 typedef struct { long double s, c; } hco_acc;
@@ -381,5 +393,101 @@ int hco_adjoint_bound_f64(const double* x, const double* y, const double* w,
         for (uint64_t i = 0; i < n2; ++i) g[i] = A[i];
     }
     free(xa); free(ya); free(W); free(F); free(T); free(A);
+    return 0;
+}
+
+/* Distribution of X1 + X2 + X3 at single output indices, by its definition:
+ * base-4 digit 0 of k admits bits (0,0,0) on that axis, digit 3 (1,1,1),
+ * digits 1 and 2 the three bit triples with that sum.  The 3^s terms (s
+ * digits equal to 1 or 2) are summed with compensation in long double. */
+void hco_sum3_direct_at_f64(const double* x1, const double* x2, const double* x3, int D,
+                            const uint64_t* ks, int64_t n, double* out)
+{
+    static const int trip[4][3][3] = {
+        {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}},
+        {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}},
+        {{0, 1, 1}, {1, 0, 1}, {1, 1, 0}},
+        {{1, 1, 1}, {1, 1, 1}, {1, 1, 1}},
+    };
+    for (int64_t r = 0; r < n; ++r) {
+        int digit[64];
+        int mid[64];
+        int s = 0;
+        uint64_t k = ks[r];
+        for (int d = 0; d < D; ++d) {
+            digit[d] = (int)(k & 3u);
+            k >>= 2;
+            if (digit[d] == 1 || digit[d] == 2) mid[s++] = d;
+        }
+        uint64_t n_terms = 1;
+        for (int c = 0; c < s; ++c) n_terms *= 3;
+        hco_acc acc = {0.0L, 0.0L};
+        for (uint64_t m = 0; m < n_terms; ++m) {
+            uint64_t i = 0, j = 0, l = 0, mm = m;
+            int c = 0;
+            for (int d = 0; d < D; ++d) {
+                int choice = 0;
+                if (c < s && mid[c] == d) { choice = (int)(mm % 3); mm /= 3; ++c; }
+                const int* b = trip[digit[d]][choice];
+                i |= (uint64_t)b[0] << d;
+                j |= (uint64_t)b[1] << d;
+                l |= (uint64_t)b[2] << d;
+            }
+            hco_acc_add(&acc, (long double)x1[i] * (long double)x2[j] * (long double)x3[l]);
+        }
+        out[r] = (double)(acc.s + acc.c);
+    }
+}
+
+/* Magnitude bounding the rounding error of the three-operand method
+ * (derived by first-order rounding analysis, like the two-operand bound):
+ *   B = |G4|(F4a|x1| . F4a|x2| . F4a|x3|),
+ *   F4a: (a0, a1) -> (a0, a0 + a1, a0 + a1, a1)
+ *   |G4|: (p0, p1, pm, pi) -> (p0, (p1 + pm)/2 + pi, (p1 + pm)/2 + p0, pi)
+ * with |computed - exact| <= (5D + 2) u B: at most D roundings per forward
+ * value, two per product and two per inverse step. */
+int hco_sum3_bound_f64(const double* x1, const double* x2, const double* x3, double* b, int D)
+{
+    if (D < 0 || D > 14) return 1;
+    const uint64_t n2 = (uint64_t)1 << D;
+    const uint64_t n4 = (uint64_t)1 << (2 * D);
+    double* f = (double*)malloc(n4 * sizeof(double));
+    double* t = (double*)malloc(n4 * sizeof(double));
+    if (!f || !t) abort();
+    const double* xs[3] = {x1, x2, x3};
+    for (int op = 0; op < 3; ++op) {
+        double* cur = (D % 2 == 0) ? f : t;
+        double* nxt = (D % 2 == 0) ? t : f;
+        for (uint64_t i = 0; i < n2; ++i) cur[i] = fabs(xs[op][i]);
+        for (int a = 0; a < D; ++a) {
+            const uint64_t n_hi = (uint64_t)1 << (2 * a);
+            const uint64_t n_lo = (uint64_t)1 << (D - a - 1);
+            for (uint64_t hi = 0; hi < n_hi; ++hi)
+                for (uint64_t lo = 0; lo < n_lo; ++lo) {
+                    const double a0 = cur[(hi * 2 + 0) * n_lo + lo];
+                    const double a1 = cur[(hi * 2 + 1) * n_lo + lo];
+                    nxt[(hi * 4 + 0) * n_lo + lo] = a0;
+                    nxt[(hi * 4 + 1) * n_lo + lo] = a0 + a1;
+                    nxt[(hi * 4 + 2) * n_lo + lo] = a0 + a1;
+                    nxt[(hi * 4 + 3) * n_lo + lo] = a1;
+                }
+            double* sw = cur; cur = nxt; nxt = sw;
+        }
+        /* cur == f now */
+        for (uint64_t k = 0; k < n4; ++k) b[k] = op == 0 ? f[k] : b[k] * f[k];
+    }
+    for (int a = D - 1; a >= 0; --a) {
+        const uint64_t n_hi = (uint64_t)1 << (2 * a);
+        const uint64_t n_lo = (uint64_t)1 << (2 * (D - a - 1));
+        for (uint64_t hi = 0; hi < n_hi; ++hi)
+            for (uint64_t lo = 0; lo < n_lo; ++lo) {
+                double* p = b + hi * 4 * n_lo + lo;
+                const double p0 = p[0], p1 = p[n_lo], pm = p[2 * n_lo], pi = p[3 * n_lo];
+                p[n_lo] = 0.5 * (p1 + pm) + pi;
+                p[2 * n_lo] = 0.5 * (p1 + pm) + p0;
+            }
+    }
+    free(f);
+    free(t);
     return 0;
 }

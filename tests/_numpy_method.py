@@ -36,3 +36,35 @@ def per_axis(x, y, *, forward_order="asc", inverse_order="desc", assoc="left",
             v[:, 1] = p1 - (p0 + p2)
         Z = v.reshape(-1)
     return Z
+
+
+def sum3_per_axis(x1, x2, x3, *, minus_point=True, halve=True, inverse_order="desc", forward_order="asc",
+                  keep_pi=False, assoc="left"):
+    """numpy transcription of the three-operand per-axis method (values at
+    0, 1, -1, infinity) with switches that plant mistakes."""
+    D = int(x1.size).bit_length() - 1
+    ops = [x1.copy(), x2.copy(), x3.copy()]
+    axes = list(range(D)) if forward_order == "asc" else list(range(D))[::-1]
+    out = []
+    for X in ops:
+        shape = [2] * D
+        for a in axes:
+            v = X.reshape(int(np.prod(shape[:a], dtype=np.int64)), 2, -1)
+            m = v[:, 0] - v[:, 1] if minus_point else v[:, 0] + v[:, 1]
+            X = np.stack([v[:, 0], v[:, 0] + v[:, 1], m, v[:, 1]], axis=1).reshape(-1)
+            shape[a] = 4
+        out.append(X)
+    Z = (out[0] * out[1]) * out[2] if assoc == "left" else out[0] * (out[1] * out[2])
+    inv_axes = list(range(D))[::-1] if inverse_order == "desc" else list(range(D))
+    two = Z.dtype.type(2) if Z.dtype.kind == "f" else 2
+    for a in inv_axes:
+        v = Z.reshape(4 ** a, 4, -1)
+        p0, p1, pm, pi = (v[:, i].copy() for i in range(4))
+        d, s = p1 - pm, p1 + pm
+        if halve:
+            d = d / two if Z.dtype.kind == "f" else d // 2
+            s = s / two if Z.dtype.kind == "f" else s // 2
+        v[:, 1] = d if keep_pi else d - pi
+        v[:, 2] = s - p0
+        Z = v.reshape(-1)
+    return Z
