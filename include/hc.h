@@ -125,6 +125,29 @@ int hc_convolve_batch(const void* x, const void* y, void* z, int D, int dtype, i
                       void* workspace, size_t workspace_bytes, hipStream_t stream);
 
 /*
+ * hc_convolve_batch for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same operation, arguments, kernels and results (bitwise) as
+ * hc_convolve_batch, but the workspace is not passed: it is a device array
+ * of HC_NOALLOC_SCRATCH_BYTES inside the library, present on every GPU the
+ * library is loaded on until the process ends.  The call allocates nothing;
+ * its first call on a device looks the array's address up on that device.
+ *   x, y, z, D, dtype, batch, stream   as hc_convolve_batch
+ * Limits: hc_workspace_bytes(D, dtype, batch) must not exceed
+ * HC_NOALLOC_SCRATCH_BYTES (float64 and int64: D <= 16 for one item, float32:
+ * D <= 17), else HC_ERR_WORKSPACE before anything is enqueued.
+ * Concurrency: every call on one GPU uses that GPU's one array, so calls
+ * whose executions overlap on one GPU (different streams, or different host
+ * threads without ordering) race and give wrong results; calls ordered on
+ * one stream are safe.  The array needs no clearing: each call writes every
+ * workspace element it reads.
+ * Errors: as hc_convolve_batch (HC_ERR_WORKSPACE as above).
+ */
+#define HC_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int hc_convolve_batch_noalloc(const void* x, const void* y, void* z, int D, int dtype, int batch,
+                              hipStream_t stream);
+
+/*
  * Workspace for hc_convolve_backward_batch, in bytes ((size_t)-1 if invalid).
  */
 size_t hc_backward_workspace_bytes(int D, int dtype, int batch);

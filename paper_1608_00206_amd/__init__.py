@@ -115,6 +115,27 @@ def convolve_batch(x: torch.Tensor, y: torch.Tensor, out: torch.Tensor | None = 
     return out
 
 
+def convolve_batch_noalloc(x: torch.Tensor, y: torch.Tensor, out: torch.Tensor) -> torch.Tensor:
+    """convolve_batch through the library's allocation-free entry point: the
+    caller passes the output, and the workspace is the library's own
+    fixed-size device array (hc_convolve_batch_noalloc in include/hc.h)."""
+    if x.dim() != 2 or x.shape != y.shape:
+        raise ValueError("x and y must both have shape (B, 2^D)")
+    if x.dtype != y.dtype:
+        raise TypeError("x and y must have the same dtype")
+    _check_device(x, y, out)
+    B, n = x.shape
+    D = dim_of(n)
+    code = _dtype_code(x)
+    if not (x.is_contiguous() and y.is_contiguous()):
+        raise ValueError("x and y must be contiguous")
+    if out.shape != (B, 3 ** D) or out.dtype != x.dtype or not out.is_contiguous():
+        raise ValueError("out must be a contiguous (B, 3^D) tensor of the input dtype")
+    _launch(x.device, _abi.hc_convolve_batch_noalloc, x.data_ptr(), y.data_ptr(), out.data_ptr(), D, code, B,
+            _stream(x.device))
+    return out
+
+
 def convolve(x: torch.Tensor, y: torch.Tensor, out: torch.Tensor | None = None,
              workspace: torch.Tensor | None = None) -> torch.Tensor:
     """z = x * y for one pair of hypercubes.

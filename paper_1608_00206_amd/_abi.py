@@ -54,6 +54,7 @@ SIGNATURES = {
     "hc_workspace_bytes": ([_I, _I, _I], _SZ),
     "hc_convolve": ([_P, _P, _P, _I, _I, _P, _SZ, _P], _I),
     "hc_convolve_batch": ([_P, _P, _P, _I, _I, _I, _P, _SZ, _P], _I),
+    "hc_convolve_batch_noalloc": ([_P, _P, _P, _I, _I, _I, _P], _I),
     "hc_backward_workspace_bytes": ([_I, _I, _I], _SZ),
     "hc_convolve_backward_batch": ([_P, _P, _P, _I64, _P, _P, _I, _I, _I, _P, _SZ, _P], _I),
     "hc_convolve_backward": ([_P, _P, _P, _P, _P, _I, _I, _P, _SZ, _P], _I),
@@ -137,6 +138,10 @@ def hc_convolve(x: int, y: int, z: int, D: int, dtype: int, ws: int, ws_bytes: i
 def hc_convolve_batch(x: int, y: int, z: int, D: int, dtype: int, batch: int, ws: int, ws_bytes: int,
                       stream: int) -> int:
     return lib().hc_convolve_batch(x, y, z, D, dtype, batch, ws, ws_bytes, stream)
+
+
+def hc_convolve_batch_noalloc(x: int, y: int, z: int, D: int, dtype: int, batch: int, stream: int) -> int:
+    return lib().hc_convolve_batch_noalloc(x, y, z, D, dtype, batch, stream)
 
 
 def hc_convolve_backward_batch(x: int, y: int, gz: int, gz_stride: int, gx: int, gy: int, D: int, dtype: int,
