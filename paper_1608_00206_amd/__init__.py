@@ -356,6 +356,7 @@ class BatchedPlan:
     def __init__(self, Ds, dtype: torch.dtype = torch.float64, tune: bool = False, persistent: bool = False):
         import json
         self._h = None
+        self._ws = None  # the plan's own workspace when the caller passes none
         self.Ds = [int(d) for d in Ds]
         self.dtype = dtype
         flags = (_abi.HC_PLAN_TUNE if tune else 0) | (_abi.HC_PLAN_PERSISTENT if persistent else 0)
@@ -388,6 +389,12 @@ class BatchedPlan:
         elif (out.numel() != self.n_outputs or out.dtype != self.dtype or not out.is_contiguous()
               or out.device != x.device):
             raise ValueError("out must be a contiguous tensor of n_outputs elements on the inputs' device")
+        if workspace is None and self.workspace_bytes > 0:
+            # kept across calls: the same buffers replay the captured graph
+            # instead of capturing it again
+            if self._ws is None or self._ws.device != x.device:
+                self._ws = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=x.device)
+            workspace = self._ws
         ws = _workspace(self.workspace_bytes, x.device, workspace)
         _launch(x.device, _abi.hc_plan_execute, self._h, x.data_ptr(), y.data_ptr(), out.data_ptr(),
                 ws.data_ptr() if ws is not None else 0, self.workspace_bytes,
@@ -402,6 +409,7 @@ class BatchedPlan:
         if self._h is not None:
             _abi.hc_plan_destroy(self._h)
             self._h = None
+        self._ws = None
 
     def __del__(self):
         try:

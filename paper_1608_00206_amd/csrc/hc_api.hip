@@ -177,6 +177,31 @@ static int default_depth(int D, int dtype)
     return 8;
 }
 
+// Groups of the outer axes [0, top) for inverse passes, in the forward
+// inverse's execution order (descending): groups of at most max_m axes,
+// filled from the top, of which at most reg in registers.
+static std::vector<InvPass> inverse_groups(int top, int reg, int max_m)
+{
+    std::vector<InvPass> out;
+    while (top > 0) {
+        const int m = top < max_m ? top : max_m;
+        const int a = top - m;
+        InvPass ip;
+        ip.a = a;
+        ip.mR = m < reg ? m : reg;
+        ip.mW = m - ip.mR;
+        // four and five axes run faster as 3 register axes plus 1 or 2 wave
+        // axes than as 4 + 0 and 4 + 1
+        if ((m == 4 || m == 5) && ip.mR == 4) {
+            ip.mR = 3;
+            ip.mW = m - 3;
+        }
+        out.push_back(ip);
+        top = a;
+    }
+    return out;
+}
+
 Plan make_plan(int D, int dtype, const PlanOpts& o)
 {
     Plan P;
@@ -190,6 +215,8 @@ Plan make_plan(int D, int dtype, const PlanOpts& o)
     P.K = K;
     P.p = D - K;
     P.grid_per_cu = o.grid_per_cu;
+    P.fused_nt = o.fused_nt == 512 ? 512 : 256;
+    P.reg_cw = (o.reg_cw == 1 || o.reg_cw == 2) ? o.reg_cw : 4;
     P.n2 = 1ull << D;
     P.n3 = pow3u(D);
     // outer forward groups (ascending), at most 4 axes each, balanced
@@ -206,23 +233,12 @@ Plan make_plan(int D, int dtype, const PlanOpts& o)
     // which at most reg axes in registers and at most 2 across waves
     const int reg = o.inv_reg > 0 ? cmin(o.inv_reg, 4) : 4;
     const int max_m = cmin(o.inv_group_max > 0 ? o.inv_group_max : 6, reg + 2);
-    int top = P.p;  // axes [0, top) still to invert
-    while (top > 0) {
-        const int m = top < max_m ? top : max_m;
-        const int a = top - m;
-        InvPass ip;
-        ip.a = a;
-        ip.mR = m < reg ? m : reg;
-        ip.mW = m - ip.mR;
-        // four and five axes run faster as 3 register axes plus 1 or 2 wave
-        // axes than as 4 + 0 and 4 + 1
-        if ((m == 4 || m == 5) && ip.mR == 4) {
-            ip.mR = 3;
-            ip.mW = m - 3;
-        }
-        P.inv.push_back(ip);
-        top = a;
-    }
+    P.inv = inverse_groups(P.p, reg, max_m);
+    // backward: the last bwd_tail outer axes get G^T inside the fused
+    // adjoint tile; the passes cover the axes above them
+    P.bwd_tail = P.p < 2 ? P.p : 2;
+    if (o.bwd_tail >= 0 && o.bwd_tail < P.bwd_tail) P.bwd_tail = o.bwd_tail;
+    P.inv_bwd = inverse_groups(P.p - P.bwd_tail, reg, max_m);
     // workspace: K1 stages ping-pong between the x~ region and a staging region
     P.xt_elems = P.p > 0 ? pow3u(P.p) << K : 0;
     P.tmp_elems = 0;
@@ -245,6 +261,9 @@ PlanOpts default_opts()
     if (const char* s = getenv("HC_INV_MAXM")) o.inv_group_max = atoi(s);
     if (const char* s = getenv("HC_INV_REG")) o.inv_reg = atoi(s);
     if (const char* s = getenv("HC_GRID_PER_CU")) o.grid_per_cu = atoi(s);
+    if (const char* s = getenv("HC_BWD_TAIL")) o.bwd_tail = atoi(s);
+    if (const char* s = getenv("HC_FUSED_NT")) o.fused_nt = atoi(s);
+    if (const char* s = getenv("HC_REG_CW")) o.reg_cw = atoi(s);
     return o;
 }
 
@@ -348,43 +367,45 @@ uint32_t tile_grid(uint64_t n_tiles, int cus, int per_cu)
     return (uint32_t)(g ? g : 1);
 }
 
-template <typename T, int K>
+template <typename T, int K, int NT>
 static void launch_fused_k(const T* xt, const T* yt, T* z, BMap in_bs, BMap z_bs, uint32_t n_tiles,
                            int batch, int cus, int per_cu, hipStream_t s)
 {
-    constexpr int NT = 256;
     dim3 grid(tile_grid(n_tiles, cus, per_cu), batch, 1);
     const double bytes = (double)batch * n_tiles * (2.0 * (1 << K) + pow3c(K)) * sizeof(T);
     LaunchScope scope(s, bytes, "fused_inner<%s,K=%d>", tname<T>(), K);
     k_fused_inner<T, K, NT><<<grid, NT, 0, s>>>(xt, yt, z, in_bs, z_bs, n_tiles);
 }
 
-template <typename T>
-int launch_fused(int K, const T* xt, const T* yt, T* z, BMap in_bs, BMap z_bs, uint32_t n_tiles,
-                  int batch, int cus, int per_cu, hipStream_t s)
+template <typename T, int K>
+static int launch_fused_nt(int nt, const T* xt, const T* yt, T* z, BMap in_bs, BMap z_bs, uint32_t n_tiles,
+                           int batch, int cus, int per_cu, hipStream_t s)
 {
-    switch (K) {
-        case 0: launch_fused_k<T, 0>(xt, yt, z, in_bs, z_bs, n_tiles, batch, cus, per_cu, s); break;
-        case 1: launch_fused_k<T, 1>(xt, yt, z, in_bs, z_bs, n_tiles, batch, cus, per_cu, s); break;
-        case 2: launch_fused_k<T, 2>(xt, yt, z, in_bs, z_bs, n_tiles, batch, cus, per_cu, s); break;
-        case 3: launch_fused_k<T, 3>(xt, yt, z, in_bs, z_bs, n_tiles, batch, cus, per_cu, s); break;
-        case 4: launch_fused_k<T, 4>(xt, yt, z, in_bs, z_bs, n_tiles, batch, cus, per_cu, s); break;
-        case 5: launch_fused_k<T, 5>(xt, yt, z, in_bs, z_bs, n_tiles, batch, cus, per_cu, s); break;
-        case 6: launch_fused_k<T, 6>(xt, yt, z, in_bs, z_bs, n_tiles, batch, cus, per_cu, s); break;
-        case 7: launch_fused_k<T, 7>(xt, yt, z, in_bs, z_bs, n_tiles, batch, cus, per_cu, s); break;
-        case 8: launch_fused_k<T, 8>(xt, yt, z, in_bs, z_bs, n_tiles, batch, cus, per_cu, s); break;
-        case 9:
-            if constexpr (sizeof(T) == 4) {
-                launch_fused_k<T, 9>(xt, yt, z, in_bs, z_bs, n_tiles, batch, cus, per_cu, s);
-                break;
-            }
-            return fail(HC_ERR_UNSUPPORTED, "no fused tile of 9 axes for 8-byte elements");
-        default: return fail(HC_ERR_UNSUPPORTED, "no fused tile of %d axes", K);
-    }
+    if (nt == 256) launch_fused_k<T, K, 256>(xt, yt, z, in_bs, z_bs, n_tiles, batch, cus, per_cu, s);
+    else if (nt == 512) launch_fused_k<T, K, 512>(xt, yt, z, in_bs, z_bs, n_tiles, batch, cus, per_cu, s);
+    else return fail(HC_ERR_UNSUPPORTED, "no fused tile with %d threads", nt);
     return HC_OK;
 }
 
-template <typename T, int K>
+template <typename T>
+int launch_fused(int K, int nt, const T* xt, const T* yt, T* z, BMap in_bs, BMap z_bs, uint32_t n_tiles,
+                 int batch, int cus, int per_cu, hipStream_t s)
+{
+#define HC_FUSED(KK) \
+    case KK: return launch_fused_nt<T, KK>(nt, xt, yt, z, in_bs, z_bs, n_tiles, batch, cus, per_cu, s);
+    switch (K) {
+        HC_FUSED(0) HC_FUSED(1) HC_FUSED(2) HC_FUSED(3) HC_FUSED(4) HC_FUSED(5) HC_FUSED(6) HC_FUSED(7)
+        HC_FUSED(8)
+        case 9:
+            if constexpr (sizeof(T) == 4)
+                return launch_fused_nt<T, 9>(nt, xt, yt, z, in_bs, z_bs, n_tiles, batch, cus, per_cu, s);
+            return fail(HC_ERR_UNSUPPORTED, "no fused tile of 9 axes for 8-byte elements");
+        default: return fail(HC_ERR_UNSUPPORTED, "no fused tile of %d axes", K);
+    }
+#undef HC_FUSED
+}
+
+template <typename T, int K, int TAIL>
 static void launch_fused_adj_k(const T* xt, const T* yt, const T* w, T* gxt, T* gyt, BMap in_bs,
                                BMap w_bs, BMap g_bs, uint32_t n_tiles, int batch, int cus, int per_cu,
                                hipStream_t s)
@@ -392,43 +413,51 @@ static void launch_fused_adj_k(const T* xt, const T* yt, const T* w, T* gxt, T* 
     constexpr int NT = 256;
     dim3 grid(tile_grid(n_tiles, cus, per_cu), batch, 1);
     const int ops = (gxt ? 1 : 0) + (gyt ? 1 : 0);
+    // every w row is counted once: the sibling rows the tail axes combine
+    // are the rows of neighbouring tiles (the same data, re-read from cache)
     const double bytes = (double)batch * n_tiles * ((2.0 + ops) * (1 << K) + pow3c(K)) * sizeof(T);
-    LaunchScope scope(s, bytes, "fused_inner_adj<%s,K=%d>", tname<T>(), K);
-    k_fused_inner_adj<T, K, NT><<<grid, NT, 0, s>>>(xt, yt, w, gxt, gyt, in_bs, w_bs, g_bs, n_tiles);
+    LaunchScope scope(s, bytes, "fused_inner_adj<%s,K=%d,t=%d>", tname<T>(), K, TAIL);
+    k_fused_inner_adj<T, K, NT, TAIL><<<grid, NT, 0, s>>>(xt, yt, w, gxt, gyt, in_bs, w_bs, g_bs, n_tiles);
 }
 
-template <typename T>
-int launch_fused_adj(int K, const T* xt, const T* yt, const T* w, T* gxt, T* gyt, BMap in_bs,
-                      BMap w_bs, BMap g_bs, uint32_t n_tiles, int batch, int cus, int per_cu, hipStream_t s)
+template <typename T, int K>
+static int launch_fused_adj_t(int tail, const T* xt, const T* yt, const T* w, T* gxt, T* gyt, BMap in_bs,
+                              BMap w_bs, BMap g_bs, uint32_t n_tiles, int batch, int cus, int per_cu,
+                              hipStream_t s)
 {
-    switch (K) {
-        case 0: launch_fused_adj_k<T, 0>(xt, yt, w, gxt, gyt, in_bs, w_bs, g_bs, n_tiles, batch, cus, per_cu, s); break;
-        case 1: launch_fused_adj_k<T, 1>(xt, yt, w, gxt, gyt, in_bs, w_bs, g_bs, n_tiles, batch, cus, per_cu, s); break;
-        case 2: launch_fused_adj_k<T, 2>(xt, yt, w, gxt, gyt, in_bs, w_bs, g_bs, n_tiles, batch, cus, per_cu, s); break;
-        case 3: launch_fused_adj_k<T, 3>(xt, yt, w, gxt, gyt, in_bs, w_bs, g_bs, n_tiles, batch, cus, per_cu, s); break;
-        case 4: launch_fused_adj_k<T, 4>(xt, yt, w, gxt, gyt, in_bs, w_bs, g_bs, n_tiles, batch, cus, per_cu, s); break;
-        case 5: launch_fused_adj_k<T, 5>(xt, yt, w, gxt, gyt, in_bs, w_bs, g_bs, n_tiles, batch, cus, per_cu, s); break;
-        case 6: launch_fused_adj_k<T, 6>(xt, yt, w, gxt, gyt, in_bs, w_bs, g_bs, n_tiles, batch, cus, per_cu, s); break;
-        case 7: launch_fused_adj_k<T, 7>(xt, yt, w, gxt, gyt, in_bs, w_bs, g_bs, n_tiles, batch, cus, per_cu, s); break;
-        case 8: launch_fused_adj_k<T, 8>(xt, yt, w, gxt, gyt, in_bs, w_bs, g_bs, n_tiles, batch, cus, per_cu, s); break;
-        case 9:
-            if constexpr (sizeof(T) == 4) {
-                launch_fused_adj_k<T, 9>(xt, yt, w, gxt, gyt, in_bs, w_bs, g_bs, n_tiles, batch, cus, per_cu, s);
-                break;
-            }
-            return fail(HC_ERR_UNSUPPORTED, "no adjoint fused tile of 9 axes for 8-byte elements");
-        default: return fail(HC_ERR_UNSUPPORTED, "no adjoint fused tile of %d axes", K);
+    switch (tail) {
+        case 0: launch_fused_adj_k<T, K, 0>(xt, yt, w, gxt, gyt, in_bs, w_bs, g_bs, n_tiles, batch, cus, per_cu, s); break;
+        case 1: launch_fused_adj_k<T, K, 1>(xt, yt, w, gxt, gyt, in_bs, w_bs, g_bs, n_tiles, batch, cus, per_cu, s); break;
+        case 2: launch_fused_adj_k<T, K, 2>(xt, yt, w, gxt, gyt, in_bs, w_bs, g_bs, n_tiles, batch, cus, per_cu, s); break;
+        default: return fail(HC_ERR_UNSUPPORTED, "no adjoint fused tile with %d tail axes", tail);
     }
     return HC_OK;
 }
 
-template <typename T, int mR, int mW, bool ADJ>
+template <typename T>
+int launch_fused_adj(int K, int tail, const T* xt, const T* yt, const T* w, T* gxt, T* gyt, BMap in_bs,
+                     BMap w_bs, BMap g_bs, uint32_t n_tiles, int batch, int cus, int per_cu, hipStream_t s)
+{
+#define HC_ADJ(KK) \
+    case KK: return launch_fused_adj_t<T, KK>(tail, xt, yt, w, gxt, gyt, in_bs, w_bs, g_bs, n_tiles, batch, cus, per_cu, s);
+    switch (K) {
+        HC_ADJ(0) HC_ADJ(1) HC_ADJ(2) HC_ADJ(3) HC_ADJ(4) HC_ADJ(5) HC_ADJ(6) HC_ADJ(7) HC_ADJ(8)
+        case 9:
+            if constexpr (sizeof(T) == 4)
+                return launch_fused_adj_t<T, 9>(tail, xt, yt, w, gxt, gyt, in_bs, w_bs, g_bs, n_tiles, batch, cus,
+                                                per_cu, s);
+            return fail(HC_ERR_UNSUPPORTED, "no adjoint fused tile of 9 axes for 8-byte elements");
+        default: return fail(HC_ERR_UNSUPPORTED, "no adjoint fused tile of %d axes", K);
+    }
+#undef HC_ADJ
+}
+
+template <typename T, int mR, int mW, int CW, bool ADJ>
 static void launch_pass_v(const T* src, T* dst, BMap src_bs, BMap dst_bs, uint64_t L, uint32_t n_hi,
                           int batch, int cus, int per_cu, hipStream_t s)
 {
-    // register-only passes take 4 waves x 64 columns per workgroup; passes
+    // register-only passes take CW waves x 64 columns per workgroup; passes
     // with a wave part take one wave per digit vector of that part
-    constexpr int CW = mW == 0 ? 4 : 1;
     using PC = PassCfg<mR, mW, CW>;
     const uint32_t tiles_per_hi = (uint32_t)((L + PC::COLS - 1) / PC::COLS);
     const uint64_t n_tiles = (uint64_t)tiles_per_hi * n_hi;
@@ -450,20 +479,25 @@ static void launch_pass_v(const T* src, T* dst, BMap src_bs, BMap dst_bs, uint64
                                                                       (uint32_t)n_tiles);
 }
 
+// cw: 64-column groups per workgroup of a register-only pass (1, 2 or 4);
+// passes with a wave part always take one.
 template <typename T, bool ADJ>
-int launch_pass(const InvPass& ip, const T* src, T* dst, BMap src_bs, BMap dst_bs, uint64_t L, uint32_t n_hi,
-                int batch, int cus, int per_cu, hipStream_t s)
+int launch_pass(const InvPass& ip, int cw, const T* src, T* dst, BMap src_bs, BMap dst_bs, uint64_t L,
+                uint32_t n_hi, int batch, int cus, int per_cu, hipStream_t s)
 {
-#define HC_PASS(R, W) \
-    if (ip.mR == R && ip.mW == W) { \
-        launch_pass_v<T, R, W, ADJ>(src, dst, src_bs, dst_bs, L, n_hi, batch, cus, per_cu, s); \
+#define HC_PASS(R, W, C) \
+    if (ip.mR == R && ip.mW == W && (W > 0 || cw == C)) { \
+        launch_pass_v<T, R, W, C, ADJ>(src, dst, src_bs, dst_bs, L, n_hi, batch, cus, per_cu, s); \
         return HC_OK; \
     }
-    HC_PASS(1, 0) HC_PASS(2, 0) HC_PASS(3, 0) HC_PASS(4, 0)
-    HC_PASS(1, 1) HC_PASS(2, 1) HC_PASS(3, 1) HC_PASS(4, 1)
-    HC_PASS(1, 2) HC_PASS(2, 2) HC_PASS(3, 2) HC_PASS(4, 2)
+    HC_PASS(1, 0, 4) HC_PASS(2, 0, 4) HC_PASS(3, 0, 4) HC_PASS(4, 0, 4)
+    HC_PASS(1, 0, 2) HC_PASS(2, 0, 2) HC_PASS(3, 0, 2) HC_PASS(4, 0, 2)
+    HC_PASS(1, 0, 1) HC_PASS(2, 0, 1) HC_PASS(3, 0, 1) HC_PASS(4, 0, 1)
+    HC_PASS(1, 1, 1) HC_PASS(2, 1, 1) HC_PASS(3, 1, 1) HC_PASS(4, 1, 1)
+    HC_PASS(1, 2, 1) HC_PASS(2, 2, 1) HC_PASS(3, 2, 1) HC_PASS(4, 2, 1)
 #undef HC_PASS
-    return fail(HC_ERR_UNSUPPORTED, "no inverse pass with %d register and %d wave axes", ip.mR, ip.mW);
+    return fail(HC_ERR_UNSUPPORTED, "no inverse pass with %d register and %d wave axes (%d column groups)", ip.mR,
+                ip.mW, cw);
 }
 
 // ------------------------------------------------------------ forward run
@@ -474,7 +508,7 @@ int run_forward(const Plan& P, const T* x, const T* y, T* z, int batch, T* ws, i
     const int D = P.D, K = P.K;
     int rc = HC_OK;
     if (P.p == 0) {
-        rc = launch_fused<T>(K, x, y, z, x_map, z_map, 1, batch, cus, P.grid_per_cu, s);
+        rc = launch_fused<T>(K, P.fused_nt, x, y, z, x_map, z_map, 1, batch, cus, P.grid_per_cu, s);
         if (rc != HC_OK) return rc;
     } else {
         T* xt = ws;
@@ -502,7 +536,8 @@ int run_forward(const Plan& P, const T* x, const T* y, T* z, int batch, T* ws, i
             c_bs = o_bs;
             a += M;
         }
-        rc = launch_fused<T>(K, xt, yt, z, P.xt_elems, z_map, (uint32_t)pow3u(P.p), batch, cus, P.grid_per_cu, s);
+        rc = launch_fused<T>(K, P.fused_nt, xt, yt, z, P.xt_elems, z_map, (uint32_t)pow3u(P.p), batch, cus,
+                             P.grid_per_cu, s);
         if (rc != HC_OK) return rc;
         for (size_t i = 0; i < P.inv.size(); ++i) {
             const InvPass& ip = P.inv[i];
@@ -517,7 +552,7 @@ int run_forward(const Plan& P, const T* x, const T* y, T* z, int batch, T* ws, i
                 }
                 if (rc != HC_ERR_UNSUPPORTED) return rc;
             }
-            rc = launch_pass<T, false>(ip, z, z, z_map, z_map, L, n_hi, batch, cus, P.grid_per_cu, s);
+            rc = launch_pass<T, false>(ip, P.reg_cw, z, z, z_map, z_map, L, n_hi, batch, cus, P.grid_per_cu, s);
             if (rc != HC_OK) return rc;
         }
     }
@@ -534,7 +569,7 @@ int run_backward(const Plan& P, const T* x, const T* y, const T* gz, uint64_t gz
     const int D = P.D, K = P.K;
     int rc = HC_OK;
     if (P.p == 0) {
-        rc = launch_fused_adj<T>(K, x, y, gz, gx, gy, P.n2, gz_bs, P.n2, 1, batch, cus, P.grid_per_cu, s);
+        rc = launch_fused_adj<T>(K, 0, x, y, gz, gx, gy, P.n2, gz_bs, P.n2, 1, batch, cus, P.grid_per_cu, s);
         if (rc != HC_OK) return rc;
     } else {
         uint64_t w_e, g_e;
@@ -548,19 +583,23 @@ int run_backward(const Plan& P, const T* x, const T* y, const T* gz, uint64_t gz
         T* gyt = gxt + (uint64_t)batch * P.xt_elems;
         T* gxtmp = gyt + (uint64_t)batch * P.xt_elems;
         T* gytmp = gxtmp + (uint64_t)batch * g_e;
-        // 1. G^T on the outer axes, ascending; the first pass reads grad_z.
-        // A broadcast grad_z (batch stride 0) gives every item the same W,
-        // computed once and read by all items.
-        const int w_items = gz_bs == 0 ? 1 : batch;
-        const uint64_t w_bs = gz_bs == 0 ? 0 : P.n3;
+        // 1. G^T on the outer axes above the tail, ascending; the first pass
+        // reads grad_z.  Without such passes the fused tiles read grad_z
+        // itself.  A broadcast grad_z (batch stride 0) gives every item the
+        // same W: it is computed once, on all outer axes (no tail), and the
+        // tiles of all items read it.
+        const bool shared = gz_bs == 0;
+        const int tail = shared ? 0 : P.bwd_tail;
+        const std::vector<InvPass>& groups = shared ? P.inv : P.inv_bwd;
+        const int w_items = shared ? 1 : batch;
         const T* src = gz;
         uint64_t src_bs = gz_bs;
-        for (int i = (int)P.inv.size() - 1; i >= 0; --i) {
-            const InvPass& ip = P.inv[i];
+        for (int i = (int)groups.size() - 1; i >= 0; --i) {
+            const InvPass& ip = groups[i];
             const int m = ip.mR + ip.mW;
             const uint64_t L = pow3u(D - ip.a - m);
             const uint32_t n_hi = (uint32_t)pow3u(ip.a);
-            rc = launch_pass<T, true>(ip, src, W, src_bs, P.n3, L, n_hi, w_items, cus, P.grid_per_cu, s);
+            rc = launch_pass<T, true>(ip, P.reg_cw, src, W, src_bs, P.n3, L, n_hi, w_items, cus, P.grid_per_cu, s);
             if (rc != HC_OK) return rc;
             src = W;
             src_bs = P.n3;
@@ -586,9 +625,11 @@ int run_backward(const Plan& P, const T* x, const T* y, const T* gz, uint64_t gz
             c_bs = o_bs;
             a += M;
         }
-        // 3. fused inner adjoint: w_hat rows -> gx~, gy~ rows
-        rc = launch_fused_adj<T>(K, xt, yt, W, gx ? gxt : nullptr, gy ? gyt : nullptr, P.xt_elems, w_bs,
-                                 P.xt_elems, (uint32_t)pow3u(P.p), batch, cus, P.grid_per_cu, s);
+        // 3. fused inner adjoint (G^T on the tail axes and the inner axes):
+        // w rows -> gx~, gy~ rows
+        const uint64_t w_bs = shared ? 0 : src_bs;
+        rc = launch_fused_adj<T>(K, tail, xt, yt, src, gx ? gxt : nullptr, gy ? gyt : nullptr, P.xt_elems,
+                                 w_bs, P.xt_elems, (uint32_t)pow3u(P.p), batch, cus, P.grid_per_cu, s);
         if (rc != HC_OK) return rc;
         // 4. F^T on the outer axes, descending groups (reverse of the forward)
         const T* ix = gxt;

@@ -59,6 +59,7 @@ struct hc_plan {
     double alg_bytes = 0;
     hipStream_t cap_stream = nullptr;
     hipEvent_t fork = nullptr;
+    hipEvent_t launched = nullptr;  // recorded after every launch of exec
     hipGraphExec_t exec = nullptr;
     const void* g_x = nullptr;
     const void* g_y = nullptr;
@@ -167,12 +168,20 @@ static int enqueue_groups(hc_plan* pl, const void* x, const void* y, void* z, vo
     return HC_OK;
 }
 
+// Destroys the instantiated graph once its last launch has finished.
+static int release_exec(hc_plan* pl)
+{
+    if (!pl->exec) return HC_OK;
+    const hipError_t e = hipEventSynchronize(pl->launched);
+    (void)hipGraphExecDestroy(pl->exec);
+    pl->exec = nullptr;
+    return e == hipSuccess ? HC_OK : hip_fail(e, "waiting for the previous graph launch");
+}
+
 static int capture(hc_plan* pl, const void* x, const void* y, void* z, void* ws)
 {
-    if (pl->exec) {
-        (void)hipGraphExecDestroy(pl->exec);
-        pl->exec = nullptr;
-    }
+    const int rc0 = release_exec(pl);
+    if (rc0 != HC_OK) return rc0;
     hipError_t e = hipStreamBeginCapture(pl->cap_stream, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
     int rc;
@@ -210,17 +219,19 @@ static int capture(hc_plan* pl, const void* x, const void* y, void* z, void* ws)
 // candidates' outputs must agree bit for bit (a disagreement means a race or
 // a bug and fails plan creation).  Results can be kept in a text cache named
 // by HC_TUNE_CACHE (one line per dtype, D and item count).
-__global__ void k_digest(const uint64_t* w, uint64_t n, unsigned long long* out)
+// Position-weighted sum of the output's 4-byte words (every element of
+// every dtype, including a trailing odd float32 element).
+__global__ void k_digest(const uint32_t* w, uint64_t n, unsigned long long* out)
 {
     uint64_t acc = 0;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
-        acc += w[i] * (2 * i + 1);
+        acc += (uint64_t)w[i] * (2 * i + 1);
     atomicAdd(out, (unsigned long long)acc);
 }
 
 static std::string cache_key(int dtype, int D, size_t items)
 {
-    return "v1:" + std::to_string(dtype) + ":" + std::to_string(D) + ":" + std::to_string(items);
+    return "v2:" + std::to_string(dtype) + ":" + std::to_string(D) + ":" + std::to_string(items);
 }
 
 static bool cache_lookup(const std::string& key, PlanOpts* o)
@@ -233,11 +244,13 @@ static bool cache_lookup(const std::string& key, PlanOpts* o)
     bool found = false;
     while (fgets(line, sizeof(line), f)) {
         char k[256];
-        int K, mm, reg;
-        if (sscanf(line, "%255s %d %d %d", k, &K, &mm, &reg) == 4 && key == k) {
+        int K, mm, reg, nt, cw;
+        if (sscanf(line, "%255s %d %d %d %d %d", k, &K, &mm, &reg, &nt, &cw) == 6 && key == k) {
             o->fused_depth = K;
             o->inv_group_max = mm;
             o->inv_reg = reg;
+            o->fused_nt = nt;
+            o->reg_cw = cw;
             found = true;
         }
     }
@@ -251,7 +264,7 @@ static void cache_store(const std::string& key, const PlanOpts& o)
     if (!path) return;
     FILE* f = fopen(path, "a");
     if (!f) return;
-    fprintf(f, "%s %d %d %d\n", key.c_str(), o.fused_depth, o.inv_group_max, o.inv_reg);
+    fprintf(f, "%s %d %d %d %d %d\n", key.c_str(), o.fused_depth, o.inv_group_max, o.inv_reg, o.fused_nt, o.reg_cw);
     fclose(f);
 }
 
@@ -269,6 +282,8 @@ static int tune_group_t(hc_plan* pl, Group& g)
                 o.fused_depth = K;
                 o.inv_reg = reg;
                 o.inv_group_max = mm;
+                o.fused_nt = 256;
+                o.reg_cw = 4;
                 cands.push_back(o);
             }
     uint64_t ws_max = 0;
@@ -299,44 +314,63 @@ static int tune_group_t(hc_plan* pl, Group& g)
     float best_ms = 1e30f;
     unsigned long long ref = 0;
     bool have_ref = false;
-    for (size_t c = 0; rc == HC_OK && c < cands.size(); ++c) {
-        const Plan P = make_plan(D, pl->dtype, cands[c]);
+    // times one candidate (a warm-up run, then three timed runs) and checks
+    // its output against the first candidate's, bit for bit
+    auto evaluate = [&](const PlanOpts& o, size_t c) -> int {
+        const Plan P = make_plan(D, pl->dtype, o);
         auto run = [&]() {
             return run_forward<T>(P, x, y, z, n, ws, pl->cus, nullptr, BMap(1ull << D), BMap(pow3u(D)));
         };
         CaptureScope quiet;  // tuning launches stay out of the profiler's record
-        if ((rc = run()) != HC_OK) break;
+        int r = run();
+        if (r != HC_OK) return r;
         (void)hipEventRecord(e0, nullptr);
-        for (int r = 0; r < 3 && rc == HC_OK; ++r) rc = run();
+        for (int k = 0; k < 3 && r == HC_OK; ++k) r = run();
         (void)hipEventRecord(e1, nullptr);
-        if (rc != HC_OK) break;
-        if ((e = hipEventSynchronize(e1)) != hipSuccess) {
-            rc = hip_fail(e, "autotuner sync");
-            break;
-        }
+        if (r != HC_OK) return r;
+        hipError_t he = hipEventSynchronize(e1);
+        if (he != hipSuccess) return hip_fail(he, "autotuner sync");
         float ms = 0;
         (void)hipEventElapsedTime(&ms, e0, e1);
         unsigned long long digest = 0;
-        e = hipMemset(dg, 0, sizeof(digest));
-        if (e == hipSuccess) {
-            k_digest<<<1024, 256>>>((const uint64_t*)z, nz * sizeof(T) / 8, dg);
-            e = hipMemcpy(&digest, dg, sizeof(digest), hipMemcpyDeviceToHost);
+        he = hipMemset(dg, 0, sizeof(digest));
+        if (he == hipSuccess) {
+            k_digest<<<1024, 256>>>((const uint32_t*)z, nz * sizeof(T) / 4, dg);
+            he = hipMemcpy(&digest, dg, sizeof(digest), hipMemcpyDeviceToHost);
         }
-        if (e != hipSuccess) {
-            rc = hip_fail(e, "autotuner digest");
-            break;
-        }
+        if (he != hipSuccess) return hip_fail(he, "autotuner digest");
         if (!have_ref) {
             ref = digest;
             have_ref = true;
         } else if (digest != ref) {
-            rc = fail(HC_ERR_HIP, "autotuner: schedule %zu for D=%d produced different bits", c, D);
-            break;
+            return fail(HC_ERR_HIP, "autotuner: schedule %zu for D=%d produced different bits", c, D);
         }
         if (ms < best_ms) {
             best_ms = ms;
-            g.opts = cands[c];
+            g.opts = o;
         }
+        return HC_OK;
+    };
+    // schedules first (fused depth, pass grouping), then the launch shapes of
+    // the best one: 512 threads per fused tile, and 1 or 2 column groups per
+    // workgroup for its register-only passes (if it has any)
+    for (size_t c = 0; rc == HC_OK && c < cands.size(); ++c) rc = evaluate(cands[c], c);
+    if (rc == HC_OK) {
+        const PlanOpts best = g.opts;
+        const Plan Pb = make_plan(D, pl->dtype, best);
+        bool reg_only = false;
+        for (const InvPass& ip : Pb.inv) reg_only |= ip.mW == 0;
+        std::vector<PlanOpts> shapes;
+        PlanOpts o = best;
+        o.fused_nt = 512;
+        shapes.push_back(o);
+        if (reg_only)
+            for (int cw : {2, 1}) {
+                o = best;
+                o.reg_cw = cw;
+                shapes.push_back(o);
+            }
+        for (size_t c = 0; rc == HC_OK && c < shapes.size(); ++c) rc = evaluate(shapes[c], cands.size() + c);
     }
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
@@ -369,9 +403,10 @@ static int tune(hc_plan* pl)
 
 static void destroy(hc_plan* pl)
 {
-    if (pl->exec) (void)hipGraphExecDestroy(pl->exec);
+    (void)release_exec(pl);
     for (Group& g : pl->groups) free_group_device(g);
     if (pl->fork) (void)hipEventDestroy(pl->fork);
+    if (pl->launched) (void)hipEventDestroy(pl->launched);
     if (pl->cap_stream) (void)hipStreamDestroy(pl->cap_stream);
     delete pl;
 }
@@ -422,6 +457,7 @@ int hc_plan_create_batched(const int* Ds, int n_pairs, int dtype, unsigned flags
     make_groups(pl);
     hipError_t e = hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&pl->fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&pl->launched, hipEventDisableTiming);
     rc = e == hipSuccess ? HC_OK : hip_fail(e, "plan stream");
     if (rc == HC_OK) {
         if (flags & HC_PLAN_TUNE) rc = tune(pl);
@@ -475,8 +511,10 @@ int hc_plan_execute(hc_plan* plan, const void* x, const void* y, void* z, void* 
     }
     const char* tn = plan->dtype == HC_F64 ? "f64" : (plan->dtype == HC_F32 ? "f32" : "i64");
     LaunchScope scope(stream, plan->alg_bytes, "batched_graph<%s>", tn);
-    const hipError_t e = hipGraphLaunch(plan->exec, stream);
+    hipError_t e = hipGraphLaunch(plan->exec, stream);
     if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    e = hipEventRecord(plan->launched, stream);
+    if (e != hipSuccess) return hip_fail(e, "graph launch event");
     return HC_OK;
 }
 
@@ -502,7 +540,8 @@ int hc_plan_describe(const hc_plan* plan, char* buf, size_t len)
                    std::to_string(ip.mW) + "\"";
         s += (i ? ", " : "") + std::string("{\"D\": ") + std::to_string(g.D) +
              ", \"items\": " + std::to_string(g.items.size()) + ", \"K\": " + std::to_string(g.plan.K) +
-             ", \"inverse_groups\": [" + inv + "]}";
+             ", \"inverse_groups\": [" + inv + "], \"fused_threads\": " + std::to_string(g.plan.fused_nt) +
+             ", \"register_pass_column_groups\": " + std::to_string(g.plan.reg_cw) + "}";
     }
     s += "]}";
     snprintf(buf, len, "%s", s.c_str());

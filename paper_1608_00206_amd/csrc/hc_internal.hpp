@@ -26,6 +26,9 @@ struct PlanOpts {
     int inv_group_max = 0;   // largest outer inverse group (at most 6)
     int inv_reg = 0;         // axes of a group held in registers (at most 4)
     int grid_per_cu = 0;     // 0: one tile per workgroup; else at most this many workgroups per CU
+    int bwd_tail = -1;       // backward: outer axes whose G^T runs in the fused tile (-1: 2)
+    int fused_nt = 0;        // threads per fused-tile workgroup (256 or 512; 0: 256)
+    int reg_cw = 0;          // 64-column groups per register-only pass workgroup (1, 2, 4; 0: 4)
 };
 
 struct Plan {
@@ -34,10 +37,14 @@ struct Plan {
     int K = 0, p = 0;                 // fused inner depth, outer axes
     std::vector<int> k1;              // outer forward groups, ascending from axis 0
     std::vector<InvPass> inv;         // outer inverse passes in execution order
+    int bwd_tail = 0;                 // backward: last outer axes transformed in the fused tile
+    std::vector<InvPass> inv_bwd;     // backward: groups of the outer axes above the tail
     uint64_t n2 = 0, n3 = 0;
     uint64_t xt_elems = 0;            // 3^p * 2^K per operand and batch item
     uint64_t tmp_elems = 0;           // largest outer-forward staging stage
     int grid_per_cu = 0;              // launch policy, see PlanOpts
+    int fused_nt = 256;               // threads per fused-tile workgroup
+    int reg_cw = 4;                   // column groups per register-only pass workgroup
 };
 
 // Brackets one kernel launch with profiler events when profiling is on.

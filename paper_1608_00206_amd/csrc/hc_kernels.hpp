@@ -620,7 +620,8 @@ __global__ __launch_bounds__(NT) void k_fwd_adj_pass(const T* __restrict__ in0, 
 
 // =========================================================================
 // Fused inner tile of the backward pass, for one outer index o:
-//   Q1  G^T on group C of w_hat[o] (thread per (gB, gA)), from global    -> W
+//   Q1  G^T on the tail outer axes and on group C of w_hat[o] (thread per
+//       (gB, gA)), from global                                           -> W
 //   Q2  G^T on group B (thread per (gC, gA))                             W -> W
 //   Q3  registers take this thread's W row (3^kA values); W is released
 //   Q0  x~[o], y~[o] -> F on groups C, B (shared with the forward)      -> R2
@@ -633,10 +634,33 @@ __global__ __launch_bounds__(NT) void k_fwd_adj_pass(const T* __restrict__ in0, 
 // the tile needs no more LDS than the forward one (FusedCfg<K>::LDS).
 // Either gradient row may be null (not requested).
 // =========================================================================
-template <typename T, int K, int NT>
+// Value of G^T on the TAIL last outer axes at one entry of row o, read from
+// the untransformed rows of the tile's siblings along those axes (rows
+// o + (e - d) * 3^(axes below) for digits e the map combines, each row
+// `rs` elements long).  dA is o's digit on the first tail axis, dB on the
+// second; the first axis is transformed before the second, as G^T runs
+// ascending.  Per axis: digit 1 keeps w1, digits 0 and 2 give w0 - w1 and
+// w2 - w1.
+template <typename T, int TAIL>
+__device__ __forceinline__ T tail_adj(const T* __restrict__ p, int dA, int dB, int64_t rs)
+{
+    if constexpr (TAIL == 0) {
+        return p[0];
+    } else if constexpr (TAIL == 1) {
+        const T w1 = p[(int64_t)(1 - dA) * rs];
+        return dA == 1 ? w1 : p[0] - w1;
+    } else {
+        auto at = [&](int eA, int eB) { return p[((int64_t)(eA - dA) * 3 + (eB - dB)) * rs]; };
+        auto u = [&](int eB) { return dA == 1 ? at(1, eB) : at(dA, eB) - at(1, eB); };
+        const T u1 = u(1);
+        return dB == 1 ? u1 : u(dB) - u1;
+    }
+}
+
+template <typename T, int K, int NT, int TAIL>
 __device__ __forceinline__ void fused_tile_adj(const T* __restrict__ xr, const T* __restrict__ yr,
                                                const T* __restrict__ wr, T* __restrict__ gxr,
-                                               T* __restrict__ gyr, T* lds)
+                                               T* __restrict__ gyr, T* lds, int dA, int dB)
 {
     using C = FusedCfg<K>;
     T* W = lds;
@@ -646,14 +670,22 @@ __device__ __forceinline__ void fused_tile_adj(const T* __restrict__ xr, const T
     constexpr int N3I = C::tC * C::tB;
     constexpr int IPT = (N3I + NT - 1) / NT;
     const int tid = threadIdx.x;
-    // Q1: G^T on group C, straight from global memory
-    for (int it = tid; it < C::tB * C::tA; it += NT) {
-        T v[pow3c(C::kC)];
+    // Q1: G^T on the tail axes (if any) and on group C, from global memory;
+    // unrolled over this thread's items so that their loads are in flight
+    // together
+    constexpr int NQ1 = C::tB * C::tA;
 #pragma unroll
-        for (int gC = 0; gC < C::tC; ++gC) v[gC] = wr[gC * (C::tB * C::tA) + it];
-        inv_adj_group<T, C::kC>(v);
+    for (int j = 0; j < (NQ1 + NT - 1) / NT; ++j) {
+        const int it = tid + j * NT;
+        if (it < NQ1) {
+            T v[pow3c(C::kC)];
 #pragma unroll
-        for (int gC = 0; gC < C::tC; ++gC) W[gC * (C::tB * C::tA) + it] = v[gC];
+            for (int gC = 0; gC < C::tC; ++gC)
+                v[gC] = tail_adj<T, TAIL>(wr + gC * NQ1 + it, dA, dB, C::N3);
+            inv_adj_group<T, C::kC>(v);
+#pragma unroll
+            for (int gC = 0; gC < C::tC; ++gC) W[gC * NQ1 + it] = v[gC];
+        }
     }
     lds_barrier();
     // Q2: G^T on group B
@@ -750,8 +782,10 @@ __device__ __forceinline__ void fused_tile_adj(const T* __restrict__ xr, const T
     }
 }
 
-template <typename T, int K, int NT>
-__global__ __launch_bounds__(NT) void k_fused_inner_adj(const T* __restrict__ xt, const T* __restrict__ yt,
+// TAIL (0, 1 or 2): the last TAIL outer axes get G^T inside the tile, from
+// w rows that have had G^T on the outer axes above them only (or none).
+template <typename T, int K, int NT, int TAIL>
+__global__ __launch_bounds__(NT, 3) void k_fused_inner_adj(const T* __restrict__ xt, const T* __restrict__ yt,
                                                         const T* __restrict__ w, T* __restrict__ gxt,
                                                         T* __restrict__ gyt, BMap in_map, BMap w_map,
                                                         BMap g_map, uint32_t n_tiles)
@@ -766,9 +800,11 @@ __global__ __launch_bounds__(NT) void k_fused_inner_adj(const T* __restrict__ xt
     const TileWalk walk = xcd_tile_walk(n_tiles);
     for (uint32_t o = walk.first; o < walk.end; o += walk.step) {
         lds_barrier();
-        fused_tile_adj<T, K, NT>(xt + (uint64_t)o * C::N2, yt + (uint64_t)o * C::N2, w + (uint64_t)o * C::N3,
-                                 gxt ? gxt + (uint64_t)o * C::N2 : nullptr,
-                                 gyt ? gyt + (uint64_t)o * C::N2 : nullptr, lds);
+        const int dB = TAIL == 2 ? (int)(o % 3u) : 0;
+        const int dA = TAIL == 2 ? (int)((o / 3u) % 3u) : (TAIL == 1 ? (int)(o % 3u) : 0);
+        fused_tile_adj<T, K, NT, TAIL>(xt + (uint64_t)o * C::N2, yt + (uint64_t)o * C::N2,
+                                       w + (uint64_t)o * C::N3, gxt ? gxt + (uint64_t)o * C::N2 : nullptr,
+                                       gyt ? gyt + (uint64_t)o * C::N2 : nullptr, lds, dA, dB);
     }
 }
 

@@ -13,11 +13,13 @@ configuration the benchmark times (default plans, tuned batched plans).
                  every output bitwise against the recursion (the other
                  default plans at large D)
   batched        4096 pairs, D uniform in {6..14}, float64 and float32, tuned
-                 plans: sampled pairs bitwise against the oracle, every pair
-                 bitwise against single-pair calls
-  backward       64 pairs at D=16, loss sum(w * z): sampled pairs bitwise
+                 plans: every pair bitwise against the oracle and against
+                 single-pair calls
+  backward       64 pairs at D=16, loss sum(w * z): every pair bitwise
                  against the transposed maps, sampled coordinates within the
-                 bound of the direct correlation, central differences
+                 bound of the direct correlation, central differences on x
+                 and y coordinates and one random direction per pair
+  D=21 float64   every output (84 GB) bitwise against the recursion
 """
 import sys
 import time
@@ -64,7 +66,9 @@ def check_against_definition(x, y, z_at, ks, D):
     tol = (4 * D + 2) * U64 * B + 2.0 ** -60 * np.abs(ref)
     err = np.abs(z_at - ref)
     assert np.all(err <= tol), f"max err/tol {np.max(err / np.maximum(tol, 1e-300))}"
-    return float(np.max(err / np.maximum(B, 1e-300)) / U64)
+    r = float(np.max(err / np.maximum(B, 1e-300)) / U64)
+    pins.error_ratio_band(r, D)
+    return r
 
 
 def test_d16_int64_matches_algorithm1():
@@ -179,24 +183,40 @@ def test_batched_4096_pairs(batched_config, dtype):
                                Z[zo[p]:zo[p + 1]].view(torch.int64 if npdt == np.float64 else torch.int32)):
                 raise AssertionError(f"pair {p} (D={Ds[p]}) differs from the single-pair call")
         torch.cuda.synchronize(DEV)
-        # sampled pairs against the oracle: every D, the largest pairs first
-        by_d = {}
-        for p, D in enumerate(Ds):
-            by_d.setdefault(D, []).append(p)
-        sample = sorted(q for D in by_d for q in by_d[D][:3])
-        worst = 0.0
-        for p in sample:
-            z = Z[zo[p]:zo[p + 1]].cpu().numpy()
-            pins.assert_bitwise(z, oracle.canonical(xs[p], ys[p]), f"pair {p} D={Ds[p]}")
-            if npdt == np.float32:
+        # every pair against the oracle (8 host threads); float32 also
+        # reports its error against the float64 oracle on 3 pairs per D
+        from concurrent.futures import ThreadPoolExecutor
+        Zh = Z.cpu().numpy()
+
+        def host_check(p):
+            pins.assert_bitwise(Zh[zo[p]:zo[p + 1]], oracle.recursive(xs[p], ys[p]), f"pair {p} D={Ds[p]}")
+            return p
+
+        t0 = time.time()
+        with ThreadPoolExecutor(8) as ex:
+            assert list(ex.map(host_check, range(len(Ds)))) == list(range(len(Ds)))
+        say(f"batched {dtype}: every pair bitwise against the oracle ({time.time() - t0:.1f} s)")
+        if npdt == np.float32:
+            by_d = {}
+            for p, D in enumerate(Ds):
+                by_d.setdefault(D, []).append(p)
+            worst = 0.0
+            for p in sorted(q for D in by_d for q in by_d[D][:3]):
+                z = Zh[zo[p]:zo[p + 1]]
                 z64 = oracle.canonical(xs[p].astype(np.float64), ys[p].astype(np.float64))
                 worst = max(worst, float(np.max(np.abs(z - z64)) / np.max(np.abs(z64))))
-        if npdt == np.float32:
             # reported, not gated: float32 against the float64 oracle
             say(f"batched float32 vs float64 oracle: max error / max|z| = {worst:.3g}")
 
 
 def test_backward_64_pairs_d16():
+    """Every one of the 64 pairs: grad_x and grad_y bitwise against the
+    transposed maps (on 8 host threads), 256 coordinates per pair within the
+    bound of the direct correlation, central differences of L = sum(w * z)
+    on 32 coordinates of x and 32 of y per pair and along one random
+    direction (x and y together) per pair.  L is bilinear, so a central
+    difference has no truncation error, only rounding."""
+    from concurrent.futures import ThreadPoolExecutor
     D, B = 16, 64
     xs = np.stack([hc_inputs.pair_masses(D, hc_inputs.W_BACKWARD, p)[0] for p in range(B)])
     ys = np.stack([hc_inputs.pair_masses(D, hc_inputs.W_BACKWARD, p)[1] for p in range(B)])
@@ -204,11 +224,13 @@ def test_backward_64_pairs_d16():
     W = torch.empty((B, 3 ** D), dtype=torch.float64, device=DEV)
     for p in range(B):
         W[p] = on_gpu(hc_inputs.loss_weights(D, hc_inputs.W_BACKWARD, p))
+    say("backward 64xD16: GPU")
     gx, gy = hc.convolve_backward(X, Y, W)
     torch.cuda.synchronize(DEV)
     gx, gy = gx.cpu().numpy(), gy.cpu().numpy()
-    for p in (0, 21, 63):
-        w = W[p].cpu().numpy()
+
+    def host_check(p):
+        w = hc_inputs.loss_weights(D, hc_inputs.W_BACKWARD, p)
         ox, oy = oracle.adjoint(xs[p], ys[p], w)
         pins.assert_bitwise(gx[p], ox, f"grad_x pair {p}")
         pins.assert_bitwise(gy[p], oy, f"grad_y pair {p}")
@@ -217,28 +239,55 @@ def test_backward_64_pairs_d16():
         bx, by = oracle.adjoint_bound(xs[p], ys[p], w)
         ii = idx.astype(np.int64)
         tol = (4 * D + 2) * U64
-        assert np.all(np.abs(gx[p][ii] - cx) <= tol * bx[ii] + 2.0 ** -60 * np.abs(cx))
-        assert np.all(np.abs(gy[p][ii] - cy) <= tol * by[ii] + 2.0 ** -60 * np.abs(cy))
-    # central differences of L = sum(w * z) on the GPU forward: L is bilinear,
-    # so the difference quotient has no truncation error, only rounding
-    p = 5
-    w = W[p]
-    x0 = X[p].clone()
+        assert np.all(np.abs(gx[p][ii] - cx) <= tol * bx[ii] + 2.0 ** -60 * np.abs(cx)), f"pair {p} x"
+        assert np.all(np.abs(gy[p][ii] - cy) <= tol * by[ii] + 2.0 ** -60 * np.abs(cy)), f"pair {p} y"
+        return p
+
+    t0 = time.time()
+    with ThreadPoolExecutor(8) as ex:
+        done = list(ex.map(host_check, range(B)))
+    assert done == list(range(B))
+    say(f"backward 64xD16: all pairs bitwise against the transposed maps ({time.time() - t0:.1f} s)")
+
     h = 1e-6
-    scale = float(np.max(np.abs(gx[p])))
-    for i in np.random.default_rng([hc_inputs.SEED, 79]).integers(0, 1 << D, 32):
-        xp = x0.clone(); xp[i] += h
-        xm = x0.clone(); xm[i] -= h
-        lp = torch.dot(hc.convolve(xp, Y[p]), w).item()
-        lm = torch.dot(hc.convolve(xm, Y[p]), w).item()
-        fd = (lp - lm) / (2 * h)
-        assert abs(fd - gx[p][i]) <= 1e-6 * scale, (i, fd, gx[p][i])
+
+    def loss(a, b, p):
+        return torch.dot(hc.convolve(a, b), W[p])
+
+    t0 = time.time()
+    for p in range(B):
+        g = np.random.default_rng([hc_inputs.SEED, 79, p])
+        ix = g.integers(0, 1 << D, 32)
+        iy = g.integers(0, 1 << D, 32)
+        x0, y0 = X[p], Y[p]
+        fds = []
+        for i in ix:
+            xp = x0.clone(); xp[i] += h
+            xm = x0.clone(); xm[i] -= h
+            fds.append((loss(xp, y0, p) - loss(xm, y0, p)) / (2 * h))
+        for i in iy:
+            yp = y0.clone(); yp[i] += h
+            ym = y0.clone(); ym[i] -= h
+            fds.append((loss(x0, yp, p) - loss(x0, ym, p)) / (2 * h))
+        vx = torch.from_numpy(g.standard_normal(1 << D)).to(DEV)
+        vy = torch.from_numpy(g.standard_normal(1 << D)).to(DEV)
+        fds.append((loss(x0 + h * vx, y0 + h * vy, p) - loss(x0 - h * vx, y0 - h * vy, p)) / (2 * h))
+        fd = torch.stack(fds).cpu().numpy()
+        sx, sy = float(np.max(np.abs(gx[p]))), float(np.max(np.abs(gy[p])))
+        assert np.all(np.abs(fd[:32] - gx[p][ix]) <= 1e-6 * sx), f"pair {p}: x coordinates"
+        assert np.all(np.abs(fd[32:64] - gy[p][iy]) <= 1e-6 * sy), f"pair {p}: y coordinates"
+        vxh, vyh = vx.cpu().numpy(), vy.cpu().numpy()
+        dd = float(gx[p] @ vxh + gy[p] @ vyh)
+        scale = float(np.linalg.norm(gx[p]) * np.linalg.norm(vxh) + np.linalg.norm(gy[p]) * np.linalg.norm(vyh))
+        assert abs(fd[64] - dd) <= 1e-9 * scale, f"pair {p}: direction {fd[64]} vs {dd}"
+    say(f"backward 64xD16: central differences on every pair ({time.time() - t0:.1f} s)")
 
 
-def test_d21_f64_maximum_size_sampled():
-    """D = 21, the largest D accepted (84 GB of float64 output): sampled
-    outputs within the certified bound of the definition, the total mass and
-    the all-zero-digits corner."""
+def test_d21_f64_every_output_bitwise():
+    """D = 21, the largest D accepted (84 GB of float64 output): every output
+    bitwise against the recursion on 16 host threads, compared in chunks;
+    sampled outputs within the certified bound of the definition, and the
+    total mass."""
     D = 21
     n3 = 3 ** D
     g = np.random.default_rng([hc_inputs.SEED, 80, D])
@@ -250,10 +299,21 @@ def test_d21_f64_maximum_size_sampled():
     z = hc.convolve(on_gpu(x), on_gpu(y))
     torch.cuda.synchronize(DEV)
     assert z.numel() == n3
+    t0 = time.time()
+    ref = oracle.recursive(x, y, threads=16)
+    say(f"D=21 float64: oracle recursion in {time.time() - t0:.1f} s; comparing")
+    chunk = 1 << 28
+    mismatches = 0
+    for c0 in range(0, n3, chunk):
+        c1 = min(n3, c0 + chunk)
+        part = z[c0:c1].cpu().numpy()
+        mismatches += int(np.count_nonzero(part.view(np.uint64) != ref[c0:c1].view(np.uint64)))
+    say(f"D=21 float64: {mismatches} of {n3} outputs differ")
+    assert mismatches == 0
+    del ref
     ks = sample_indices(D, 256, 3)
     z_at = z[torch.from_numpy(ks.astype(np.int64)).to(DEV)].cpu().numpy()
     r = check_against_definition(x, y, z_at, ks, D)
-    assert z_at[0] == x[0] * y[0] and z_at[-1] == x[-1] * y[-1]
     total = float(z.sum().item())
     assert abs(total - float(x.sum()) * float(y.sum())) < 1e-12
     say(f"D=21 float64: max |err|/(u B) over {ks.size} sampled outputs = {r:.2f}; sum z - 1 = {total - 1:.2e}")
