@@ -125,6 +125,35 @@ int hc_convolve_batch(const void* x, const void* y, void* z, int D, int dtype, i
                       void* workspace, size_t workspace_bytes, hipStream_t stream);
 
 /*
+ * Distribution of a sum of three independent random vectors X1 + X2 + X3
+ * whose D axes are all Bernoulli (Introduction: sums of multiple probability
+ * mass functions whose axes are Bernoulli variables; the sum of two is
+ * hc_convolve itself):
+ *   z[k] = sum over i, j, l in {0,1}^D with i + j + l = k of
+ *          (x1[i] * x2[j]) * x3[l],
+ * every digit of k in {0, 1, 2, 3}.  Computed by the Methods section's
+ * per-axis method extended to three operands: along one axis each operand is
+ * a linear polynomial a0 + a1 t and their product a cubic, recovered from its
+ * values at t = 0, 1, -1 and infinity (the only division is by 2, exact in
+ * binary floating point outside the subnormal range):
+ *   forward  (a0, a1) -> (a0, a0 + a1, a0 - a1, a1)              axes 0..D-1
+ *   product  (x1^ * x2^) * x3^                                   elementwise
+ *   inverse  (p0, p1, pm, pi) -> (p0, (p1 - pm)/2 - pi,
+ *                                 (p1 + pm)/2 - p0, pi)           axes D-1..0
+ * each one IEEE operation in this order.  int64 data wraps modulo 2^64 and
+ * halves by signed division; exact whenever every intermediate fits in int64.
+ *   x1, x2, x3   device, batch x 2^D elements each (read only; layout as x)
+ *   z            device, batch x 4^D elements (written); base-4 digit d of
+ *                the flat index (weight 4^d) is the coordinate on axis D-1-d
+ *   workspace    hc_sum3_workspace_bytes(D, dtype, batch) bytes
+ * 0 <= D <= 16, 1 <= batch <= 65535.
+ * Errors: as hc_convolve_batch (HC_ERR_D_RANGE above D = 16).
+ */
+size_t hc_sum3_workspace_bytes(int D, int dtype, int batch);  /* (size_t)-1 if invalid */
+int hc_sum3_batch(const void* x1, const void* x2, const void* x3, void* z, int D, int dtype, int batch,
+                  void* workspace, size_t workspace_bytes, hipStream_t stream);
+
+/*
  * hc_convolve_batch for callers that cannot allocate device memory (code
  * under HIP graph capture, tight serving loops, harnesses that forbid
  * hipMalloc).  Same operation, arguments, kernels and results (bitwise) as

@@ -260,6 +260,43 @@ def difference_batch(x: torch.Tensor, y: torch.Tensor, out: torch.Tensor | None 
     return out
 
 
+def sum3_batch(x1: torch.Tensor, x2: torch.Tensor, x3: torch.Tensor, out: torch.Tensor | None = None,
+               workspace: torch.Tensor | None = None) -> torch.Tensor:
+    """Distribution of X1 + X2 + X3 for (B, 2^D) distributions over {0,1}^D:
+    base-4 digit d of an output index is the sum of the three coordinates on
+    axis D-1-d.  Returns (B, 4^D)."""
+    if x1.dim() != 2 or x1.shape != x2.shape or x1.shape != x3.shape:
+        raise ValueError("x1, x2 and x3 must all have shape (B, 2^D)")
+    if not (x1.dtype == x2.dtype == x3.dtype):
+        raise TypeError("x1, x2 and x3 must have the same dtype")
+    _check_device(x1, x2, x3)
+    B, n = x1.shape
+    D = dim_of(n)
+    code = _dtype_code(x1)
+    x1, x2, x3 = x1.contiguous(), x2.contiguous(), x3.contiguous()
+    if out is None:
+        out = torch.empty((B, 4 ** D), dtype=x1.dtype, device=x1.device)
+    elif out.shape != (B, 4 ** D) or out.dtype != x1.dtype or not out.is_contiguous() or out.device != x1.device:
+        raise ValueError("out must be a contiguous (B, 4^D) tensor of the input dtype")
+    nbytes = _abi.hc_sum3_workspace_bytes(D, code, B)
+    if nbytes == _abi.SIZE_MAX:
+        raise ValueError("invalid D, dtype or batch for sum3")
+    ws = _workspace(nbytes, x1.device, workspace)
+    _launch(x1.device, _abi.hc_sum3_batch, x1.data_ptr(), x2.data_ptr(), x3.data_ptr(), out.data_ptr(), D, code, B,
+            ws.data_ptr() if ws is not None else 0, nbytes, _stream(x1.device))
+    return out
+
+
+def sum3(x1: torch.Tensor, x2: torch.Tensor, x3: torch.Tensor, out: torch.Tensor | None = None,
+         workspace: torch.Tensor | None = None) -> torch.Tensor:
+    """Single-triple form of sum3_batch: (2^D,) inputs, (4^D,) output."""
+    if x1.dim() != 1:
+        raise ValueError("x1, x2 and x3 must be 1-D tensors of length 2^D")
+    n = x1.numel()
+    flat = out.view(1, -1) if out is not None else None
+    return sum3_batch(x1.view(1, n), x2.view(1, n), x3.view(1, n), out=flat, workspace=workspace).view(-1)
+
+
 def difference(x: torch.Tensor, y: torch.Tensor, out: torch.Tensor | None = None,
                workspace: torch.Tensor | None = None) -> torch.Tensor:
     """Single-pair form of difference_batch: (2^D,) inputs, (3^D,) output."""

@@ -208,6 +208,27 @@ def test_maxconv_validation():
     assert f(x, y, x + 8, 10, 0, 1, 2.0, 0, ws, big, 0) == 4             # z overlaps x
 
 
+def test_sum3_validation():
+    x1, x2, x3, z, ws = FAKE, FAKE + (1 << 22), FAKE + (1 << 23), FAKE + (1 << 26), FAKE + (1 << 34)
+    f = _abi.hc_sum3_batch
+    big = 1 << 30
+    # workspace: six staging copies of 4^p 2^K entries per item (K = 5 for
+    # 8-byte data, 6 for float32), none when everything fits one tile
+    assert _abi.hc_sum3_workspace_bytes(5, _abi.HC_F64, 1) == 0
+    assert _abi.hc_sum3_workspace_bytes(10, _abi.HC_F64, 2) == 2 * 6 * (1 << 15) * 8
+    assert _abi.hc_sum3_workspace_bytes(10, _abi.HC_F32, 1) == 6 * (1 << 14) * 4
+    assert _abi.hc_sum3_workspace_bytes(17, _abi.HC_F64, 1) == _abi.SIZE_MAX
+    assert _abi.hc_sum3_workspace_bytes(8, 9, 1) == _abi.SIZE_MAX
+    assert f(0, x2, x3, z, 8, 0, 1, ws, big, 0) == 1              # null input
+    assert f(x1, x2, x3, z, 17, 0, 1, ws, big, 0) == 2            # D above 16
+    assert f(x1, x2, x3, z, 8, 7, 1, ws, big, 0) == 3             # dtype
+    assert f(x1, x2, x3, z, 8, 0, 0, ws, big, 0) == 1             # batch 0
+    assert f(x1 + 4, x2, x3, z, 8, 0, 1, ws, big, 0) == 5         # misaligned
+    assert f(x1, x2, x3, z, 8, 0, 1, 0, 0, 0) == 6                # workspace missing
+    assert f(x1, x2, x3, x3 + 8, 8, 0, 1, ws, big, 0) == 4        # z overlaps x3
+    assert f(x1, x2, x3, z, 8, 0, 1, z + 64, big, 0) == 4         # workspace overlaps z
+
+
 def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     """Without libhc.so the binding raises instead of computing anything
     another way (there is no CPU fallback)."""
