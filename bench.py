@@ -11,8 +11,10 @@ HIP-event-timed duration on the launch stream, against the 8 TB/s HBM peak),
 and the CPU oracle timed on a bounded sample of the same workload.
 
 Workloads (inputs from hc_inputs, seeded and synthetic):
-  all       (default) d20 as the headline value, plus batched, backward and
-            apps measured after it and reported under "secondary"
+  all       (default) d20 as the headline value, plus d10, d16-f64,
+            d16-i64 (each with every output compared to the oracle),
+            batched, backward and apps measured after it and reported under
+            "secondary"
   d20       one pair, D=20, float64 masses (3^20 outputs)
   d20-f32   the same pair in float32
   d16-f64   one pair, D=16, float64 masses
@@ -22,7 +24,8 @@ Workloads (inputs from hc_inputs, seeded and synthetic):
   backward  64 pairs at D=16 float64, forward + backward of sum(w * z)
   apps      carry-free convolution of two length-10^6 vectors, the
             distribution of X - Y and the p-norm max-convolution (p = 32),
-            both at D=20 (float64)
+            both at D=20 (float64), and the distribution of X1 + X2 + X3
+            at D=14 (float64, 4^14 outputs)
 """
 from __future__ import annotations
 
@@ -222,7 +225,7 @@ def cpu_baseline(x, y, z_gpu, D):
     import numpy as np
 
     import oracle
-    threads = min(16, os.cpu_count() or 1)
+    threads = host_threads()
     out = np.empty(3 ** D, dtype=x.dtype)
     log(f"cpu baseline: oracle recursion D={D} on {threads} threads")
     t0 = time.perf_counter()
@@ -251,9 +254,19 @@ def cpu_baseline(x, y, z_gpu, D):
     return {"value": round(3 ** D / dt, 1), "unit": "output elems/s", "cores": threads, "kind": "oracle",
             "sample": f"the whole workload (one D={D} pair), three-subproblem recursion",
             "seconds": round(dt, 3), "gpu_output_bitwise_equal": equal, "cpu_model": cpu_model(),
+            "host_nproc": os.cpu_count(), "host_cpus_allowed": len(os.sched_getaffinity(0)),
             "single_thread": {"value": round(3 ** Ds / dt1, 1), "unit": "output elems/s", "cores": 1,
                               "sample": f"one D={Ds} float64 pair of the same distribution",
                               "seconds": round(dt1, 3)}}
+
+
+# Host CPUs the job may use: every CPU the process is allowed to run on, at
+# most 16 (the host CPU share that comes with one GPU of the machine).
+HOST_CPU_SHARE = 16
+
+
+def host_threads() -> int:
+    return max(1, min(HOST_CPU_SHARE, len(os.sched_getaffinity(0))))
 
 
 def cpu_model() -> str:
@@ -267,7 +280,7 @@ def cpu_model() -> str:
     return "unknown"
 
 
-def run_single(args, torch, hc, D, dtype_name):
+def run_single(args, torch, hc, D, dtype_name, steps=None, warmup=None, cpu=True, parity=False):
     import numpy as np
 
     import hc_inputs
@@ -297,21 +310,33 @@ def run_single(args, torch, hc, D, dtype_name):
     def step():
         hc.convolve(tx, ty, out=z, workspace=ws)
 
-    ms, wall, stats = time_steps(step, args.steps, args.warmup, torch)
-    log(f"timed {args.steps} steps: {ms:.3f} ms/step (wall {wall:.3f} s)")
+    steps = steps or args.steps
+    warmup = args.warmup if warmup is None else warmup
+    ms, wall, stats = time_steps(step, steps, warmup, torch)
+    log(f"timed {steps} steps: {ms:.3f} ms/step (wall {wall:.3f} s)")
     n_out = 3 ** D
+    wl_name = {("f64", 20): "d20", ("f32", 20): "d20-f32", ("f64", 16): "d16-f64", ("i64", 16): "d16-i64",
+               ("f64", 10): "d10"}.get((dtype_name, D), f"d{D}-{dtype_name}")
     res = {
         "metric": METRIC, "value": round(n_out / (ms / 1e3), 1), "unit": "output elems/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True,
+        "steps": steps, "warmup": warmup, "ms_per_step": round(ms, 4), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": dtype_name, "data": "synthetic",
         "config": {"workload": desc, "D": D, "outputs_per_step": n_out, "global_batch": 1,
                    "parallelism": "single GPU"},
-        "roofline": roofline(stats, args.steps, args.workload if args.workload != "all" else "d20"),
+        "roofline": roofline(stats, steps, wl_name),
         "compulsory_hbm_frac": round((n_out + 2 * (1 << D)) * z.element_size() / (ms / 1e3) / 1e9
                                      / HBM_PEAK_GBS, 4),
-        "kernels": kernel_table(stats, args.steps),
+        "kernels": kernel_table(stats, steps),
     }
-    if not args.no_cpu_baseline:
+    if parity:
+        # every output bitwise against the oracle's recursion (which the CPU
+        # tests pin to Algorithm 1 and to the per-axis method)
+        import oracle
+        ref = oracle.recursive(x, y, threads=host_threads())
+        iv = np.int32 if ref.dtype.itemsize == 4 else np.int64
+        res["oracle_bitwise_equal"] = bool(np.array_equal(z.cpu().numpy().view(iv), ref.view(iv)))
+        log(f"{wl_name}: every output bitwise equal to the oracle: {res['oracle_bitwise_equal']}")
+    if cpu and not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(x, y, z, D)
     del z, ws
     return res
@@ -359,6 +384,17 @@ def run_apps(args, torch, hc, steps=None, warmup=None):
                                   "output_elems_per_s": round(3 ** D / (ms / 1e3), 1),
                                   "kernels": kernel_table(st, steps)}
     del x, y, z, ws
+    torch.cuda.empty_cache()
+    # distribution of X1 + X2 + X3 (three Bernoulli-axis vectors), D = 14
+    D = 14
+    xs = [torch.from_numpy(hc_inputs.masses(D, hc_inputs.W_D16, 0, role)).to(dev) for role in range(3)]
+    z = torch.empty(4 ** D, dtype=torch.float64, device=dev)
+    ws = torch.empty(max(hc._abi.hc_sum3_workspace_bytes(D, hc._abi.HC_F64, 1), 1), dtype=torch.uint8, device=dev)
+    ms, _, st = time_steps(lambda: hc.sum3(*xs, out=z, workspace=ws), steps, warmup, torch)
+    log(f"sum of three D={D}: {ms:.3f} ms/step")
+    out["sum3_D14_f64"] = {"D": D, "ms_per_step": round(ms, 4), "output_elems_per_s": round(4 ** D / (ms / 1e3), 1),
+                           "kernels": kernel_table(st, steps)}
+    del xs, z, ws
     torch.cuda.empty_cache()
     return out
 
@@ -535,7 +571,15 @@ def main():
             # outside its timed region
             torch.cuda.empty_cache()
             sec_steps = max(2, min(args.steps, 5))
-            res["secondary"] = {"batched_4096_pairs": run_batched(args, torch, hc, sec_steps, 1),
+            single = {}
+            for name, Dq, dq, n_steps in (("d10_f64", 10, "f64", 200), ("d16_f64", 16, "f64", 20),
+                                          ("d16_i64", 16, "i64", 20)):
+                r = run_single(args, torch, hc, Dq, dq, n_steps, 5, cpu=False, parity=True)
+                single[name] = {k: r[k] for k in ("value", "unit", "ms_per_step", "steps", "dtype", "config",
+                                                  "roofline", "kernels", "oracle_bitwise_equal")}
+            torch.cuda.empty_cache()
+            res["secondary"] = {**single,
+                                "batched_4096_pairs": run_batched(args, torch, hc, sec_steps, 1),
                                 "backward_64xD16_f64": run_backward(args, torch, hc, sec_steps, 1),
                                 "applications": run_apps(args, torch, hc, sec_steps, 1)}
     print(json.dumps(res), flush=True)
