@@ -332,7 +332,13 @@ int hc_difference_batch(const void* x, const void* y, void* z, int D, int dtype,
  * which lies between max_{pairs} x[i] y[j] and 2^(s/p) times it (s = number
  * of digits of k equal to 1).  Computed as mx my (conv((x/mx)^p, (y/my)^p))^(1/p)
  * with mx, my each input's maximum and the convolution of this library;
- * negative entries count as 0.  Limits: powers below the smallest float
+ * negative entries count as 0.  Integer p in [1, 1024] form (x/mx)^p from the
+ * quotient in float64 by binary powering on double-double values (the
+ * squares of x/mx selected by the bits of p, low bits first, each product
+ * kept to about twice float64 precision with fused multiply-adds), rounded
+ * once to the data type: a relative error of about one rounding, in a fixed
+ * order of operations; other p use the device library's pow.
+ * Limits: powers below the smallest float
  * vanish (outputs below about mx my * 2^(-1074/p) for float64 read 0), and the
  * inverse map's cancellation leaves a relative error of about
  * (4D+2) u B/(p z'), B the method's rounding bound of the powered inputs, so

@@ -133,12 +133,61 @@ __device__ __forceinline__ T pow_t(T a, T b)
     else return pow(a, b);
 }
 
+// a^k for an integer k >= 1 by binary powering: the result accumulates the
+// squares a, a^2, a^4, ... selected by the bits of k, low bits first (each
+// product one IEEE multiplication in this order).
+template <typename T>
+__device__ __forceinline__ T int_pow(T a, int k)
+{
+    T A = T(1), b = a;
+    for (;;) {
+        if (k & 1) A *= b;
+        k >>= 1;
+        if (!k) break;
+        b *= b;
+    }
+    return A;
+}
+
+// (xh + xl) <- (xh + xl)(yh + yl) on double-double values: the product's
+// rounding error and the cross terms are gathered with fused multiply-adds,
+// then renormalised (|e| is far below |p|, so the fast two-sum is exact).
+__device__ __forceinline__ void dd_mul(double& xh, double& xl, double yh, double yl)
+{
+    const double p = xh * yh;
+    double e = fma(xh, yh, -p);
+    e = fma(xh, yl, e);
+    e = fma(xl, yh, e);
+    const double h = p + e;
+    xl = e - (h - p);
+    xh = h;
+}
+
+// q^k for an integer k >= 1 in float64 with one final rounding of a
+// double-double result: binary powering (the squares q, q^2, q^4, ...
+// selected by the bits of k, low bits first), every product by dd_mul.
+// Relative error about u, about what a correctly rounded pow gives, in a
+// fixed order of IEEE operations.
+__device__ __forceinline__ double pow_dd(double q, int k)
+{
+    double Ah = 1.0, Al = 0.0, bh = q, bl = 0.0;
+    for (;;) {
+        if (k & 1) dd_mul(Ah, Al, bh, bl);
+        k >>= 1;
+        if (!k) break;
+        dd_mul(bh, bl, bh, bl);
+    }
+    return Ah + Al;
+}
+
 // xp[b][i] = (x[b][i] / mx_b)^p, yp likewise (0 where the entry or the scale
-// is not positive).  blockIdx.y = item, blockIdx.z = operand.
+// is not positive).  Integer p (ip > 0) take pow_dd on the quotient formed in
+// float64 (rounded once to T at the end); other p take the device library's
+// pow.  blockIdx.y = item, blockIdx.z = operand.
 template <typename T>
 __global__ __launch_bounds__(APP_NT) void k_power(const T* __restrict__ x, const T* __restrict__ y,
                                                   T* __restrict__ xp, T* __restrict__ yp,
-                                                  const T* __restrict__ scales, uint64_t n2, T p)
+                                                  const T* __restrict__ scales, uint64_t n2, T p, int ip)
 {
     const int op = blockIdx.z;
     const uint64_t off = (uint64_t)blockIdx.y * n2;
@@ -147,7 +196,12 @@ __global__ __launch_bounds__(APP_NT) void k_power(const T* __restrict__ x, const
     const T m = scales[(uint64_t)op * gridDim.y + blockIdx.y];
     for (uint64_t i = (uint64_t)blockIdx.x * APP_NT + threadIdx.x; i < n2; i += (uint64_t)gridDim.x * APP_NT) {
         const T v = src[i];
-        dst[i] = (v > T(0) && m > T(0)) ? pow_t<T>(v / m, p) : T(0);
+        T r = T(0);
+        if (v > T(0) && m > T(0)) {
+            if (ip > 0) r = (T)pow_dd((double)v / (double)m, ip);
+            else r = pow_t<T>(v / m, p);
+        }
+        dst[i] = r;
     }
 }
 
@@ -173,6 +227,7 @@ constexpr int ROOT_INT_MAX = 1024;
 struct RootCoef {
     double c[4];
     float inv_pf;  // 1/p rounded to float, for the seed
+    int log2p;     // log2(p) when p is a power of two
 };
 
 // v^(1/p) for finite v > 0 and integer 2 <= p <= ROOT_INT_MAX, in float64.
@@ -184,7 +239,10 @@ struct RootCoef {
 // below), eps = V / A - 1 (V - A is exact, |eps| < 1e-3), and
 // V^(1/p) = a (1 + eps)^(1/p), the series cut after eps^4.  The result is
 // within 2 u of the exact root, with a margin of 10x on the seed's error.
-__device__ __forceinline__ double root_int(double v, int p, const RootCoef& rc)
+// POW2: p = 2^log2p, so that a^p is log2p squarings (the same products, in
+// the same order, as the binary powering below gives for such p).
+template <bool POW2>
+__device__ __forceinline__ double root_int(double v, int p, int log2p, const RootCoef& rc)
 {
     int e;
     const double m = frexp(v, &e);
@@ -192,12 +250,12 @@ __device__ __forceinline__ double root_int(double v, int p, const RootCoef& rc)
     const int rem = e - n * p;
     const float t = ((float)rem + __builtin_amdgcn_logf((float)m)) * rc.inv_pf;
     const double a = (double)__builtin_amdgcn_exp2f(t);
-    double A = 1.0, b = a;
-    for (int k = p;;) {
-        if (k & 1) A *= b;
-        k >>= 1;
-        if (!k) break;
-        b *= b;
+    double A;
+    if constexpr (POW2) {
+        A = a;
+        for (int k = 0; k < log2p; ++k) A *= A;
+    } else {
+        A = int_pow<double>(a, p);
     }
     const double V = ldexp(m, rem);
     double q = __builtin_amdgcn_rcp(A);
@@ -208,23 +266,27 @@ __device__ __forceinline__ double root_int(double v, int p, const RootCoef& rc)
 }
 
 // How k_root takes the root: p = 1 needs none; integer p in
-// [2, ROOT_INT_MAX] take root_int (in float64 for both types); other p take
+// [2, ROOT_INT_MAX] take root_int (in float64 for both types; powers of two
+// with the squaring loop, the same products); other p take
 // exp(log(v) / p), whose relative error is a few ulps times
 // 1 + |ln v| / p.  Either error is far below the estimate's own 2^(s/p) bias.
-enum RootMode { ROOT_NONE = 0, ROOT_INT = 1, ROOT_EXPLOG = 2 };
+enum RootMode { ROOT_NONE = 0, ROOT_INT = 1, ROOT_EXPLOG = 2, ROOT_POW2 = 3 };
 
 // mx my max(v, 0)^(1/p) for one output (s = mx my), optionally rounded.
+// The root is taken on every lane (of 1 where v <= 0) and the result
+// selected, so that no lane waits for a branch around the arithmetic.
 template <typename T, int MODE>
 __device__ __forceinline__ T root_value(T v, T s, T inv_p, int ip, const RootCoef& rc, int round)
 {
-    T r = T(0);
-    if (v > T(0)) {
-        T w;
-        if constexpr (MODE == ROOT_NONE) w = v;
-        else if constexpr (MODE == ROOT_INT) w = (T)root_int((double)v, ip, rc);
-        else w = exp_t<T>(log_t<T>(v) * inv_p);
-        r = s * w;
-    }
+    const bool pos = v > T(0);
+    const T vv = pos ? v : T(1);
+    T w;
+    if constexpr (MODE == ROOT_NONE) w = vv;
+    else if constexpr (MODE == ROOT_INT) w = (T)root_int<false>((double)vv, ip, rc.log2p, rc);
+    else if constexpr (MODE == ROOT_POW2) w = (T)root_int<true>((double)vv, ip, rc.log2p, rc);
+    else w = exp_t<T>(log_t<T>(vv) * inv_p);
+    const T sw = s * w;
+    T r = pos ? sw : T(0);
     if (round) r = rint(r);
     return r;
 }
@@ -336,13 +398,15 @@ static int maxconv_t(const T* x, const T* y, T* z, int D, int batch, double p, b
         k_maxscale_part<T><<<dim3(MAXSCALE_PARTS, batch, 2), MAX_NT, 0, s>>>(x, y, n2, part);
         k_maxscale_final<T><<<dim3(batch, 2, 1), MAX_NT, 0, s>>>(part, scales);
     }
+    const int ip = (p == std::floor(p) && p >= 2 && p <= ROOT_INT_MAX) ? (int)p : 0;
     {
         LaunchScope scope(s, 4.0 * batch * n2 * sizeof(T), "power<%s>", tname<T>());
-        k_power<T><<<dim3(copy_grid(n2, cus), batch, 2), APP_NT, 0, s>>>(x, y, xp, yp, scales, n2, (T)p);
+        // p = 1 is the scaled value itself (pow_dd with k = 1)
+        k_power<T><<<dim3(copy_grid(n2, cus), batch, 2), APP_NT, 0, s>>>(x, y, xp, yp, scales, n2, (T)p,
+                                                                          p == 1 ? 1 : ip);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "max-convolution launch");
-    const int ip = (p == std::floor(p) && p >= 2 && p <= ROOT_INT_MAX) ? (int)p : 0;
     RootCoef coef{};
     const double c1 = 1.0 / p;
     coef.c[0] = c1;
@@ -350,13 +414,17 @@ static int maxconv_t(const T* x, const T* y, T* z, int D, int batch, double p, b
     coef.c[2] = coef.c[1] * (c1 - 2) / 3;
     coef.c[3] = coef.c[2] * (c1 - 3) / 4;
     coef.inv_pf = (float)c1;
+    coef.log2p = 0;
+    while (ip > 1 && (1 << (coef.log2p + 1)) <= ip) ++coef.log2p;
+    const bool pow2 = ip >= 2 && (1 << coef.log2p) == ip;
     const T inv_p = (T)c1;
     const int rnd = round ? 1 : 0;
-    const int mode = p == 1 ? ROOT_NONE : (ip ? ROOT_INT : ROOT_EXPLOG);
+    const int mode = p == 1 ? ROOT_NONE : (pow2 ? ROOT_POW2 : (ip ? ROOT_INT : ROOT_EXPLOG));
     // the root runs as the epilogue of the convolution's last inverse pass
     // where that pass has an epilogue kernel, else as its own kernel
     const RootEpilogue<T, ROOT_NONE> e_none{scales, batch, inv_p, ip, coef, rnd};
     const RootEpilogue<T, ROOT_INT> e_int{scales, batch, inv_p, ip, coef, rnd};
+    const RootEpilogue<T, ROOT_POW2> e_pow2{scales, batch, inv_p, ip, coef, rnd};
     const RootEpilogue<T, ROOT_EXPLOG> e_explog{scales, batch, inv_p, ip, coef, rnd};
     LastPass last;
     if (mode == ROOT_NONE) {
@@ -365,6 +433,9 @@ static int maxconv_t(const T* x, const T* y, T* z, int D, int batch, double p, b
     } else if (mode == ROOT_INT) {
         last.launch = launch_root_pass<T, ROOT_INT>;
         last.ctx = &e_int;
+    } else if (mode == ROOT_POW2) {
+        last.launch = launch_root_pass<T, ROOT_POW2>;
+        last.ctx = &e_pow2;
     } else {
         last.launch = launch_root_pass<T, ROOT_EXPLOG>;
         last.ctx = &e_explog;
@@ -377,6 +448,7 @@ static int maxconv_t(const T* x, const T* y, T* z, int D, int batch, double p, b
         const dim3 grid((uint32_t)((n3 + ROOT_SPAN - 1) / ROOT_SPAN), batch, 1);
         if (mode == ROOT_NONE) k_root<T, ROOT_NONE><<<grid, APP_NT, 0, s>>>(z, scales, n3, inv_p, ip, coef, rnd);
         else if (mode == ROOT_INT) k_root<T, ROOT_INT><<<grid, APP_NT, 0, s>>>(z, scales, n3, inv_p, ip, coef, rnd);
+        else if (mode == ROOT_POW2) k_root<T, ROOT_POW2><<<grid, APP_NT, 0, s>>>(z, scales, n3, inv_p, ip, coef, rnd);
         else k_root<T, ROOT_EXPLOG><<<grid, APP_NT, 0, s>>>(z, scales, n3, inv_p, ip, coef, rnd);
     }
     e = hipGetLastError();

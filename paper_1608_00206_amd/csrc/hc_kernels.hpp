@@ -641,19 +641,31 @@ __global__ __launch_bounds__(NT) void k_fwd_adj_pass(const T* __restrict__ in0, 
 // second; the first axis is transformed before the second, as G^T runs
 // ascending.  Per axis: digit 1 keeps w1, digits 0 and 2 give w0 - w1 and
 // w2 - w1.
+// Every operand is loaded unconditionally (a digit 1 makes two of the
+// addresses coincide) and the result is selected, so that the loads of many
+// entries are in flight together instead of waiting behind branches.
 template <typename T, int TAIL>
 __device__ __forceinline__ T tail_adj(const T* __restrict__ p, int dA, int dB, int64_t rs)
 {
     if constexpr (TAIL == 0) {
         return p[0];
     } else if constexpr (TAIL == 1) {
+        const T own = p[0];
         const T w1 = p[(int64_t)(1 - dA) * rs];
-        return dA == 1 ? w1 : p[0] - w1;
+        const T diff = own - w1;
+        return dA == 1 ? w1 : diff;
     } else {
-        auto at = [&](int eA, int eB) { return p[((int64_t)(eA - dA) * 3 + (eB - dB)) * rs]; };
-        auto u = [&](int eB) { return dA == 1 ? at(1, eB) : at(dA, eB) - at(1, eB); };
-        const T u1 = u(1);
-        return dB == 1 ? u1 : u(dB) - u1;
+        const T a = p[0];                                           // (dA, dB)
+        const T b = p[(int64_t)(1 - dA) * 3 * rs];                  // (1, dB)
+        const T c = p[(int64_t)(1 - dB) * rs];                      // (dA, 1)
+        const T d = p[((int64_t)(1 - dA) * 3 + (1 - dB)) * rs];     // (1, 1)
+        // axis A: u(e) = w[dA, e] - w[1, e], or w[1, e] when dA = 1
+        const T uab = a - b, ucd = c - d;
+        const T uB = dA == 1 ? b : uab;
+        const T u1 = dA == 1 ? d : ucd;
+        // axis B
+        const T diff = uB - u1;
+        return dB == 1 ? u1 : diff;
     }
 }
 

@@ -339,3 +339,78 @@ def test_maxconv_batch_and_errors():
         hc.maxconv_pnorm(on_gpu(np.ones(4, dtype=np.int64)), on_gpu(np.ones(4, dtype=np.int64)), 2.0)
     with pytest.raises(hc.HCError):
         hc.maxconv_pnorm(on_gpu(np.ones(4)), on_gpu(np.ones(4)), 0.5)
+
+
+def fma_exact(a, b, c):
+    """Correctly rounded a*b + c, elementwise, by exact rational arithmetic."""
+    from fractions import Fraction
+    return np.array([float(Fraction(float(x)) * Fraction(float(y)) + Fraction(float(z)))
+                     for x, y, z in zip(a, b, c)], dtype=np.float64)
+
+
+def pow_dd_host(q, k):
+    """q^k as the library forms integer powers: binary powering on
+    double-double values, each product p = xh*yh, e = fma(xh, yh, -p),
+    e = fma(xh, yl, e), e = fma(xl, yh, e), h = p + e, l = e - (h - p), and
+    the result h + l rounded once (float64 throughout)."""
+    q = np.asarray(q, dtype=np.float64)
+
+    def mul(xh, xl, yh, yl):
+        p = xh * yh
+        e = fma_exact(xh, yh, -p)
+        e = fma_exact(xh, yl, e)
+        e = fma_exact(xl, yh, e)
+        h = p + e
+        return h, e - (h - p)
+
+    Ah, Al = np.ones_like(q), np.zeros_like(q)
+    bh, bl = q.copy(), np.zeros_like(q)
+    while True:
+        if k & 1:
+            Ah, Al = mul(Ah, Al, bh, bl)
+        k >>= 1
+        if not k:
+            return Ah + Al
+        bh, bl = mul(bh, bl, bh, bl)
+
+
+@pytest.mark.parametrize("dtype,p", [(np.float64, 1.0), (np.float64, 2.0), (np.float64, 3.0), (np.float64, 8.0),
+                                     (np.float64, 32.0), (np.float64, 77.0), (np.float32, 2.0),
+                                     (np.float32, 8.0)])
+@pytest.mark.parametrize("kind", ["mass", "signed"])
+@pytest.mark.parametrize("separate", [False, True])
+def test_maxconv_exact_power_stage(dtype, p, kind, separate):
+    """Integer p: the library forms (x / mx)^p by binary powering on
+    double-double values in a fixed order, which the host reproduces exactly
+    (its fused multiply-adds in exact rational arithmetic); the powered
+    convolution on the GPU is then the oracle's canonical convolution of
+    them (bitwise, as everywhere), and the estimate differs from the
+    correctly rounded mx my (that convolution)^(1/p) by the root's own error
+    only: at most 2 ulps for the polished root (float64 arithmetic, in both
+    dtypes) plus the rounding of the scaling; none at p = 1.  Entries whose
+    powered convolution is not positive give 0."""
+    from decimal import Decimal, getcontext
+    D = 10
+    x, y = hc_inputs.random_pair(D, dtype, 11 + int(p), kind=kind)
+    z = hc.maxconv_pnorm(on_gpu(x), on_gpu(y), p, separate_root=separate)
+    torch.cuda.synchronize(DEV)
+    z = z.cpu().numpy()
+    pos = lambda v: np.where(v > 0, v, np.zeros_like(v))
+    mx, my = pos(x).max(), pos(y).max()
+    powered = lambda v, m: np.where(v > 0, pow_dd_host(v.astype(np.float64) / np.float64(m), int(p)),
+                                    0.0).astype(dtype)
+    conv = oracle.canonical(powered(x, mx), powered(y, my))
+    s = dtype(mx) * dtype(my)
+    if p == 1.0:
+        pins.assert_bitwise(z, np.where(conv > 0, s * conv, np.zeros_like(conv)), "p = 1")
+        return
+    getcontext().prec = 40
+    inv_p = Decimal(1) / Decimal(int(p))
+    c64 = conv.astype(np.float64)
+    root = np.array([float(Decimal(float(c)) ** inv_p) if c > 0 else 0.0 for c in c64])
+    expect = float(s) * root
+    ulp = np.spacing(np.abs(expect).astype(dtype)).astype(np.float64)
+    err = np.abs(z.astype(np.float64) - expect) / ulp
+    allowed = 3.5 if np.dtype(dtype) == np.float64 else 1.5
+    assert np.all(z[c64 <= 0] == 0)
+    assert np.max(err) <= allowed, f"max error {np.max(err):.2f} ulp"
