@@ -93,15 +93,49 @@ struct FusedCfg {
 // Forward half shared by the fused forward and the fused adjoint: loads the
 // two rows and applies F on groups C and B, leaving x and y in R2 with layout
 // [bA][gC][gB] (so that P3's reads are consecutive across lanes).
+// Rows held in registers (entries tid, tid + NT, ... of each): the adjoint
+// tile loads them before its w row, so that both loads are in flight at once.
+template <typename T, int K, int NT>
+struct RowRegs {
+    static constexpr int N = (FusedCfg<K>::N2 + NT - 1) / NT;
+    T x[N], y[N];
+    __device__ __forceinline__ void load(const T* __restrict__ xr, const T* __restrict__ yr)
+    {
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            const int i = (int)threadIdx.x + j * NT;
+            if (i < FusedCfg<K>::N2) {
+                x[j] = xr[i];
+                y[j] = yr[i];
+            }
+        }
+    }
+};
+
+template <typename T, int K, int NT>
+__device__ __forceinline__ void fused_forward_cb_from(const RowRegs<T, K, NT>& rows, T* R0, T* R1, T* R2);
+
 template <typename T, int K, int NT>
 __device__ __forceinline__ void fused_forward_cb(const T* __restrict__ xr, const T* __restrict__ yr,
                                                  T* R0, T* R1, T* R2)
 {
+    RowRegs<T, K, NT> rows;
+    rows.load(xr, yr);
+    fused_forward_cb_from<T, K, NT>(rows, R0, R1, R2);
+}
+
+template <typename T, int K, int NT>
+__device__ __forceinline__ void fused_forward_cb_from(const RowRegs<T, K, NT>& rows, T* R0, T* R1, T* R2)
+{
     using C = FusedCfg<K>;
     const int tid = threadIdx.x;
-    for (int i = tid; i < C::N2; i += NT) {
-        R0[i] = xr[i];
-        R0[C::R0h + i] = yr[i];
+#pragma unroll
+    for (int j = 0; j < RowRegs<T, K, NT>::N; ++j) {
+        const int i = tid + j * NT;
+        if (i < C::N2) {
+            R0[i] = rows.x[j];
+            R0[C::R0h + i] = rows.y[j];
+        }
     }
     lds_barrier();
     // P1: F on group C
@@ -682,6 +716,9 @@ __device__ __forceinline__ void fused_tile_adj(const T* __restrict__ xr, const T
     constexpr int N3I = C::tC * C::tB;
     constexpr int IPT = (N3I + NT - 1) / NT;
     const int tid = threadIdx.x;
+    // the x~, y~ rows are loaded first and held in registers until Q0
+    RowRegs<T, K, NT> rows;
+    rows.load(xr, yr);
     // Q1: G^T on the tail axes (if any) and on group C, from global memory;
     // unrolled over this thread's items so that their loads are in flight
     // together
@@ -726,7 +763,7 @@ __device__ __forceinline__ void fused_tile_adj(const T* __restrict__ xr, const T
         }
     }
     lds_barrier();
-    fused_forward_cb<T, K, NT>(xr, yr, R0, R1, R2);
+    fused_forward_cb_from<T, K, NT>(rows, R0, R1, R2);
     // Q3': each thread's R2 columns are read and rewritten by that thread only
 #pragma unroll
     for (int j = 0; j < IPT; ++j) {

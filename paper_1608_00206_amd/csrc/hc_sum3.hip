@@ -185,11 +185,27 @@ __global__ __launch_bounds__(S3_NT) void k_s3_fused(const T* __restrict__ r0, co
     const int tid = threadIdx.x;
     const uint64_t item = blockIdx.y;
     const TileWalk w = xcd_tile_walk(n_tiles);
+    constexpr int RPT = (C::N2 + S3_NT - 1) / S3_NT;  // row entries per thread
     for (uint32_t o = w.first; o < w.end; o += w.step) {
+        // the three rows' loads are issued together, before any LDS work
+        T rv[3][RPT];
+#pragma unroll
         for (int op = 0; op < 3; ++op) {
             const T* row = (op == 0 ? r0 : (op == 1 ? r1 : r2)) + item * r_bs + (uint64_t)o * C::N2;
+#pragma unroll
+            for (int j = 0; j < RPT; ++j) {
+                const int i = tid + j * S3_NT;
+                rv[op][j] = i < C::N2 ? row[i] : T(0);
+            }
+        }
+#pragma unroll
+        for (int op = 0; op < 3; ++op) {
             __syncthreads();  // the previous operand's product reads of its buffer are done
-            for (int i = tid; i < C::N2; i += S3_NT) A[i] = row[i];
+#pragma unroll
+            for (int j = 0; j < RPT; ++j) {
+                const int i = tid + j * S3_NT;
+                if (i < C::N2) A[i] = rv[op][j];
+            }
             __syncthreads();
             T* cur = A;
             T* nxt = B;
