@@ -14,12 +14,12 @@
 
 using namespace hc;
 
-namespace {
-
 // Host code must never pass this name to a kernel: on the host it is a
 // stand-in, not a device address.  Its address on each device comes from
 // hipGetSymbolAddress and is kept in g_scratch_ptr.
-__device__ __align__(256) unsigned char scratch[HC_NOALLOC_SCRATCH_BYTES];
+static __device__ __align__(256) unsigned char scratch[HC_NOALLOC_SCRATCH_BYTES];
+
+namespace {
 
 constexpr int kMaxDevices = 64;
 std::mutex g_mu;
