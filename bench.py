@@ -110,8 +110,10 @@ def profiler_name(demangled: str):
     if base == "inv_pass":
         kind = "inv_adj_pass" if args[3] == "true" else "inv_pass"
         return f"{kind}<{dt},{args[0]}+{args[1]}>"
-    if base in ("fused_inner", "fused_inner_adj"):
+    if base == "fused_inner":
         return f"{base}<{dt},K={args[0]}>"
+    if base == "fused_inner_adj":
+        return f"{base}<{dt},K={args[0]},t={args[2]}>"
     if base in ("fwd_pass", "fwd_adj_pass"):
         return f"{base}<{dt},M={args[0]}>"
     return None
