@@ -27,7 +27,8 @@
 //                   operands: 2^D -> 4^p x 2^K each              (k_s3_fwd)
 //   fused inner     per outer index o: F4 on the K inner axes of the three
 //                   rows in LDS, the product, G4 on the inner axes, one
-//                   contiguous 4^K row of z                      (k_s3_fused)
+//                   contiguous 4^K row of z (K = 5; the two innermost
+//                   axes in registers)                         (k_s3_fused_r)
 //   outer inverse   G4 on axes p-1..0 in groups of at most 3, in place
 //                                                                (k_s3_inv)
 #include "hc.h"
@@ -253,7 +254,120 @@ __global__ __launch_bounds__(S3_NT) void k_s3_fused(const T* __restrict__ r0, co
     }
 }
 
-int fused_depth(int D, size_t es) { return D < (es == 4 ? 6 : 5) ? D : (es == 4 ? 6 : 5); }
+// The same tile for K >= 2 with its two innermost axes in registers: the
+// forward steps on axes 0..K-3 run in LDS for the three operands together;
+// then one thread per (outer digits, digit of axis K-2) reads the 2 x 2
+// binary sub-cube of each operand, applies F4 on axis K-2 (its own digit)
+// and K-1, multiplies the operands, applies G4 on axis K-1 and writes four
+// contiguous entries; G4 on axes K-2..0 then runs in LDS.  Every entry
+// sees the same operations in the same order as in the tile above.
+template <typename T>
+__device__ __forceinline__ T f4_at(int g, T a0, T a1)
+{
+    const T s = a0 + a1;
+    const T d = a0 - a1;
+    return (g & 2) ? ((g & 1) ? a1 : d) : ((g & 1) ? s : a0);
+}
+
+template <typename T, int K>
+__global__ __launch_bounds__(S3_NT) void k_s3_fused_r(const T* __restrict__ r0, const T* __restrict__ r1,
+                                                      const T* __restrict__ r2, T* __restrict__ z, uint64_t r_bs,
+                                                      uint64_t z_bs, uint32_t n_tiles)
+{
+    static_assert(K >= 2, "two register axes");
+    constexpr int N2 = 1 << K, N4 = 1 << (2 * K);
+    constexpr int NS = 1 << (2 * (K - 1));  // forward state after K-2 steps: 4^(K-2) x 2 x 2
+    __shared__ T SA[3 * NS];
+    __shared__ T SB[3 * NS];
+    __shared__ T P[N4];
+    const int tid = threadIdx.x;
+    const uint64_t item = blockIdx.y;
+    const TileWalk w = xcd_tile_walk(n_tiles);
+    constexpr int RPT = (N2 + S3_NT - 1) / S3_NT;
+    for (uint32_t o = w.first; o < w.end; o += w.step) {
+        T rv[3][RPT];
+#pragma unroll
+        for (int op = 0; op < 3; ++op) {
+            const T* row = (op == 0 ? r0 : (op == 1 ? r1 : r2)) + item * r_bs + (uint64_t)o * N2;
+#pragma unroll
+            for (int j = 0; j < RPT; ++j) {
+                const int i = tid + j * S3_NT;
+                rv[op][j] = i < N2 ? row[i] : T(0);
+            }
+        }
+        __syncthreads();  // the previous tile's reads of SA, SB and P are done
+#pragma unroll
+        for (int op = 0; op < 3; ++op)
+#pragma unroll
+            for (int j = 0; j < RPT; ++j) {
+                const int i = tid + j * S3_NT;
+                if (i < N2) SA[op * NS + i] = rv[op][j];
+            }
+        __syncthreads();
+        T* cur = SA;
+        T* nxt = SB;
+#pragma unroll
+        for (int a = 0; a + 2 < K; ++a) {
+            // per operand [4^a][2][2^(K-a-1)] -> [4^a][4][2^(K-a-1)]
+            const int lo_n = 1 << (K - a - 1);
+            const int n = (1 << (2 * a)) * lo_n;
+            for (int idx = tid; idx < 3 * n; idx += S3_NT) {
+                const int op = idx / n, r = idx - op * n;
+                const int hi = r / lo_n, lo = r - hi * lo_n;
+                const T* c = cur + op * NS;
+                T* d = nxt + op * NS;
+                const T a0 = c[(hi * 2 + 0) * lo_n + lo];
+                const T a1 = c[(hi * 2 + 1) * lo_n + lo];
+                d[(hi * 4 + 0) * lo_n + lo] = a0;
+                d[(hi * 4 + 1) * lo_n + lo] = a0 + a1;
+                d[(hi * 4 + 2) * lo_n + lo] = a0 - a1;
+                d[(hi * 4 + 3) * lo_n + lo] = a1;
+            }
+            __syncthreads();
+            T* t = cur;
+            cur = nxt;
+            nxt = t;
+        }
+        // registers: thread (hi, g) with g the digit of axis K-2
+        for (int t = tid; t < NS; t += S3_NT) {
+            const int hi = t >> 2, g = t & 3;
+            T prod[4];
+#pragma unroll
+            for (int op = 0; op < 3; ++op) {
+                const T* c = cur + op * NS + hi * 4;  // [b(K-2)][b(K-1)]
+                const T v0 = f4_at<T>(g, c[0], c[2]);
+                const T v1 = f4_at<T>(g, c[1], c[3]);
+                const T f[4] = {v0, v0 + v1, v0 - v1, v1};
+#pragma unroll
+                for (int e = 0; e < 4; ++e) prod[e] = op == 0 ? f[e] : prod[e] * f[e];
+            }
+            g4(prod[0], prod[1], prod[2], prod[3]);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) P[t * 4 + e] = prod[e];
+        }
+        __syncthreads();
+        // G4 on axes K-2 .. 0, in place on P
+#pragma unroll
+        for (int a = K - 2; a >= 0; --a) {
+            const int lo_n = 1 << (2 * (K - a - 1));
+            const int n = (1 << (2 * a)) * lo_n;
+            for (int idx = tid; idx < n; idx += S3_NT) {
+                const int hi = idx / lo_n, lo = idx - hi * lo_n;
+                T* p = P + hi * 4 * lo_n + lo;
+                T p0 = p[0], p1 = p[lo_n], pm = p[2 * lo_n], pi = p[3 * lo_n];
+                g4(p0, p1, pm, pi);
+                p[lo_n] = p1;
+                p[2 * lo_n] = pm;
+            }
+            __syncthreads();
+        }
+        T* zr = z + item * z_bs + (uint64_t)o * N4;
+        for (int i = tid; i < N4; i += S3_NT) zr[i] = P[i];
+    }
+}
+
+// Inner axes per fused tile (the tile's LDS: 20 KB for 8-byte data)
+int fused_depth(int D) { return D < 5 ? D : 5; }
 
 struct S3Plan {
     int D = 0, K = 0, p = 0;
@@ -266,7 +380,7 @@ S3Plan make_s3_plan(int D, size_t es)
 {
     S3Plan P;
     P.D = D;
-    P.K = fused_depth(D, es);
+    P.K = fused_depth(D);
     P.p = D - P.K;
     P.n2 = 1ull << D;
     P.n4 = 1ull << (2 * D);
@@ -308,7 +422,10 @@ void launch_fused(const T* r0, const T* r1, const T* r2, T* z, uint64_t r_bs, ui
     dim3 grid(tile_grid(n_tiles, cus, 0), batch, 1);
     LaunchScope scope(s, (double)batch * n_tiles * (3.0 * (1 << K) + (1 << (2 * K))) * sizeof(T),
                       "s3_fused<%s,K=%d>", tname<T>(), K);
-    k_s3_fused<T, K><<<grid, S3_NT, 0, s>>>(r0, r1, r2, z, r_bs, z_bs, n_tiles);
+    if constexpr (K >= 2)
+        k_s3_fused_r<T, K><<<grid, S3_NT, 0, s>>>(r0, r1, r2, z, r_bs, z_bs, n_tiles);
+    else
+        k_s3_fused<T, K><<<grid, S3_NT, 0, s>>>(r0, r1, r2, z, r_bs, z_bs, n_tiles);
 }
 
 template <typename T>
@@ -347,12 +464,7 @@ int run_s3(const S3Plan& P, const T* x1, const T* x2, const T* x3, T* z, int bat
         case 3: launch_fused<T, 3>(c0, c1, c2, z, c_bs, P.n4, n_tiles, batch, cus, s); break;
         case 4: launch_fused<T, 4>(c0, c1, c2, z, c_bs, P.n4, n_tiles, batch, cus, s); break;
         case 5: launch_fused<T, 5>(c0, c1, c2, z, c_bs, P.n4, n_tiles, batch, cus, s); break;
-        default:
-            if constexpr (sizeof(T) == 4) {
-                launch_fused<T, 6>(c0, c1, c2, z, c_bs, P.n4, n_tiles, batch, cus, s);
-                break;
-            }
-            return fail(HC_ERR_UNSUPPORTED, "no three-operand tile of %d axes", P.K);
+        default: return fail(HC_ERR_UNSUPPORTED, "no three-operand tile of %d axes", P.K);
     }
     // outer inverse: groups descending from the innermost outer axis
     int top = P.p;
