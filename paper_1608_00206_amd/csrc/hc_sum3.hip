@@ -25,12 +25,14 @@
 // GPU schedule, mirroring the two-operand path:
 //   outer forward   F4 on axes 0..p-1 in groups of at most 3, for the three
 //                   operands: 2^D -> 4^p x 2^K each              (k_s3_fwd)
-//   fused inner     per outer index o: F4 on the K inner axes of the three
-//                   rows in LDS, the product, G4 on the inner axes, one
-//                   contiguous 4^K row of z (K = 5; the two innermost
-//                   axes in registers)                         (k_s3_fused_r)
-//   outer inverse   G4 on axes p-1..0 in groups of at most 3, in place
-//                                                                (k_s3_inv)
+//   fused inner     per outer index o: F4 on the K = 6 inner axes of the
+//                   three rows, the product, G4 on the inner axes, one
+//                   contiguous 4^K row of z, every step on two axes held
+//                   in registers                                 (k_s3_tile6)
+//                   (D < 6: one tile of D axes,      k_s3_fused_r / k_s3_fused)
+//   outer inverse   G4 on axes p-1..0 in place: p mod 4 axes in registers
+//                   (k_s3_inv), then groups of 4: three axes in registers,
+//                   the fourth across the workgroup's waves    (k_s3_inv4w)
 #include "hc.h"
 
 #include <hip/hip_runtime.h>
@@ -166,6 +168,62 @@ __global__ __launch_bounds__(S3_NT) void k_s3_inv(T* __restrict__ z, uint64_t z_
         if (has_mid_digit(t, M)) p[(uint64_t)t * L] = v[t];
 }
 
+// Outer inverse on four axes in place, waves across the outermost axis: z
+// viewed as [n_hi][4^4][L], L a multiple of 64.  A workgroup of four waves
+// takes 64 consecutive columns; wave w holds digit w of the group's
+// outermost axis and its lanes' 64 registers the three inner axes (row
+// 64 w + t for register index t), so every load and store moves one
+// contiguous 64-column segment of a row.  G4 runs on the three inner axes in
+// registers (descending), then on the outermost axis through LDS in four
+// sub-rounds of 16 register indices: every wave writes its 16 values, and
+// wave w then takes indices 4w .. 4w+3 with all four digits.  Entries G4
+// leaves unchanged are not written back.
+template <typename T>
+__global__ __launch_bounds__(S3_NT) void k_s3_inv4w(T* __restrict__ z, uint64_t z_bs, uint32_t n_tiles,
+                                                    uint32_t tiles_per_hi, uint32_t log2L)
+{
+    __shared__ T S[4 * 16 * 64];
+    const uint32_t tile = blockIdx.x;
+    if (tile >= n_tiles) return;  // the whole workgroup
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const uint64_t L = 1ull << log2L;
+    const uint32_t hi = tile / tiles_per_hi, j = tile - hi * tiles_per_hi;
+    char* tbase = reinterpret_cast<char*>(z + (uint64_t)blockIdx.y * z_bs + (uint64_t)hi * 256 * L + (uint64_t)j * 64);
+    const uint64_t row = L * sizeof(T);
+    const uint32_t off = (uint32_t)lane * (uint32_t)sizeof(T);
+    constexpr uint32_t SEG = 64 * sizeof(T);
+    T v[64];
+    {
+        const char* rp = tbase + (uint64_t)w * 64 * row;
+#pragma unroll
+        for (int t = 0; t < 64; ++t) v[t] = buf_load<T>(row_rsrc(rp + t * row, SEG), off);
+    }
+    g4_group<T, 3>(v);
+    char* wbase = tbase;
+    asm volatile("" : "+s"(wbase));
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        if (r > 0) __syncthreads();  // the previous sub-round's reads are done
+#pragma unroll
+        for (int k = 0; k < 16; ++k) S[(w * 16 + k) * 64 + lane] = v[16 * r + k];
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int k = 4 * w + q;
+            const int t = 16 * r + k;
+            T p0 = S[(0 * 16 + k) * 64 + lane], p1 = S[(1 * 16 + k) * 64 + lane];
+            T pm = S[(2 * 16 + k) * 64 + lane], pi = S[(3 * 16 + k) * 64 + lane];
+            g4(p0, p1, pm, pi);
+            const bool t_mid = has_mid_digit(t, 3);
+            if (t_mid) buf_store<T>(row_rsrc(wbase + (uint64_t)t * row, SEG), off, p0);
+            buf_store<T>(row_rsrc(wbase + (uint64_t)(64 + t) * row, SEG), off, p1);
+            buf_store<T>(row_rsrc(wbase + (uint64_t)(128 + t) * row, SEG), off, pm);
+            if (t_mid) buf_store<T>(row_rsrc(wbase + (uint64_t)(192 + t) * row, SEG), off, pi);
+        }
+    }
+}
+
 // Fused inner tile: for outer index o, the three rows r_op[o] (2^K values
 // each) -> F4 on the K inner axes (ascending) in LDS -> product -> G4 on the
 // inner axes (descending) -> z[o] (4^K values, contiguous).
@@ -277,9 +335,13 @@ __global__ __launch_bounds__(S3_NT) void k_s3_fused_r(const T* __restrict__ r0, 
     static_assert(K >= 2, "two register axes");
     constexpr int N2 = 1 << K, N4 = 1 << (2 * K);
     constexpr int NS = 1 << (2 * (K - 1));  // forward state after K-2 steps: 4^(K-2) x 2 x 2
-    __shared__ T SA[3 * NS];
-    __shared__ T SB[3 * NS];
-    __shared__ T P[N4];
+    // LDS: region X (three operands at stride NS) and region Y (4 NS); the
+    // forward steps alternate between them and end in X, so that the
+    // product's 4^K entries go to Y while X is read
+    __shared__ T S[7 * NS];
+    T* const X = S;
+    T* const Y = S + 3 * NS;
+    T* const P = Y;
     const int tid = threadIdx.x;
     const uint64_t item = blockIdx.y;
     const TileWalk w = xcd_tile_walk(n_tiles);
@@ -295,17 +357,17 @@ __global__ __launch_bounds__(S3_NT) void k_s3_fused_r(const T* __restrict__ r0, 
                 rv[op][j] = i < N2 ? row[i] : T(0);
             }
         }
-        __syncthreads();  // the previous tile's reads of SA, SB and P are done
+        __syncthreads();  // the previous tile's reads of P are done
 #pragma unroll
         for (int op = 0; op < 3; ++op)
 #pragma unroll
             for (int j = 0; j < RPT; ++j) {
                 const int i = tid + j * S3_NT;
-                if (i < N2) SA[op * NS + i] = rv[op][j];
+                if (i < N2) (((K - 2) & 1) ? Y : X)[op * NS + i] = rv[op][j];
             }
         __syncthreads();
-        T* cur = SA;
-        T* nxt = SB;
+        T* cur = ((K - 2) & 1) ? Y : X;
+        T* nxt = ((K - 2) & 1) ? X : Y;
 #pragma unroll
         for (int a = 0; a + 2 < K; ++a) {
             // per operand [4^a][2][2^(K-a-1)] -> [4^a][4][2^(K-a-1)]
@@ -366,14 +428,158 @@ __global__ __launch_bounds__(S3_NT) void k_s3_fused_r(const T* __restrict__ r0, 
     }
 }
 
-// Inner axes per fused tile (the tile's LDS: 20 KB for 8-byte data)
-int fused_depth(int D) { return D < 5 ? D : 5; }
+// F4 on one axis of a pair of values, all four outputs
+template <typename T>
+__device__ __forceinline__ void f4_pair(T a0, T a1, T& o0, T& o1, T& o2, T& o3)
+{
+    o0 = a0;
+    o1 = a0 + a1;
+    o2 = a0 - a1;
+    o3 = a1;
+}
+
+// F4 on two axes of a 2 x 2 block held by one thread, the outer axis first:
+// x[b * 2 + b'] -> y[g * 4 + g'] (g, g' the digits of the outer, inner axis)
+template <typename T>
+__device__ __forceinline__ void f4_two(const T (&x)[4], T (&y)[16])
+{
+    T u[4][2];
+#pragma unroll
+    for (int b1 = 0; b1 < 2; ++b1) f4_pair(x[b1], x[2 + b1], u[0][b1], u[1][b1], u[2][b1], u[3][b1]);
+#pragma unroll
+    for (int g0 = 0; g0 < 4; ++g0) f4_pair(u[g0][0], u[g0][1], y[g0 * 4 + 0], y[g0 * 4 + 1], y[g0 * 4 + 2], y[g0 * 4 + 3]);
+}
+
+// G4 on two axes of 16 values held by one thread (index g * 4 + g'), the
+// inner axis first
+template <typename T>
+__device__ __forceinline__ void g4_two(T (&q)[16])
+{
+#pragma unroll
+    for (int g0 = 0; g0 < 4; ++g0) g4(q[g0 * 4 + 0], q[g0 * 4 + 1], q[g0 * 4 + 2], q[g0 * 4 + 3]);
+#pragma unroll
+    for (int g1 = 0; g1 < 4; ++g1) g4(q[0 * 4 + g1], q[1 * 4 + g1], q[2 * 4 + g1], q[3 * 4 + g1]);
+}
+
+// Fused tile of six inner axes, 256 threads, every step on two axes at once.
+// Tile digits: axes 0..5 of the tile with digits g0..g5; the output row is
+// z[o][b * 256 + c * 16 + a] with b = (g0, g1), c = (g2, g3), a = (g4, g5)
+// (each pair as 4 g + g').  Steps, each followed by a barrier:
+//   forward on axes 0, 1   48 threads (operand, binary digits of axes 2..5)
+//   forward on axes 2, 3   192 threads (operand, binary axes 4, 5, b)
+//   forward on axes 4, 5, the product, G4 on axes 5, 4: thread (b, c)
+//   G4 on axes 3, 2:       thread (a, b), in place
+//   G4 on axes 1, 0:       thread (a, c), stored to z (coalesced)
+// LDS holds 4096 values: the product array P[a][b][c] at
+// a * 256 + (b ^ (c & 1)) * 16 + (c ^ a), a layout in which each of the
+// three access patterns above meets 32 distinct 8-byte banks per 32 lanes;
+// the forward states sit in the same memory ahead of it.
+template <typename T>
+__global__ __launch_bounds__(S3_NT) void k_s3_tile6(const T* __restrict__ r0, const T* __restrict__ r1,
+                                                    const T* __restrict__ r2, T* __restrict__ z, uint64_t r_bs,
+                                                    uint64_t z_bs, uint32_t n_tiles)
+{
+    static_assert(S3_NT == 256, "one thread per (b, c), (a, b) and (a, c)");
+    __shared__ T S[4096];
+    T* const A = S;          // input rows [op][64]                        (192)
+    T* const C = S;          // after axes 0..3: [op][k][g01 * 16 + (g23 ^ g01)]  (3072)
+    T* const B = S + 3072;   // after axes 0, 1: [op][g01 * 16 + (lo ^ g01)]      (768)
+    T* const P = S;
+    const int tid = threadIdx.x;
+    const uint64_t item = blockIdx.y;
+    const TileWalk w = xcd_tile_walk(n_tiles);
+    for (uint32_t o = w.first; o < w.end; o += w.step) {
+        T in = T(0);
+        if (tid < 192) {
+            const int op = tid >> 6;
+            const T* row = (op == 0 ? r0 : (op == 1 ? r1 : r2)) + item * r_bs + (uint64_t)o * 64;
+            in = row[tid & 63];
+        }
+        __syncthreads();  // the previous tile's reads of P are done
+        if (tid < 192) A[tid] = in;
+        __syncthreads();
+        if (tid < 48) {
+            // F4 on axes 0, 1 for binary digits lo of axes 2..5
+            const int op = tid >> 4, lo = tid & 15;
+            const T* a = A + op * 64;
+            const T x[4] = {a[lo], a[16 + lo], a[32 + lo], a[48 + lo]};
+            T y[16];
+            f4_two(x, y);
+            T* b = B + op * 256;
+#pragma unroll
+            for (int g01 = 0; g01 < 16; ++g01) b[g01 * 16 + (lo ^ g01)] = y[g01];
+        }
+        __syncthreads();
+        if (tid < 192) {
+            // F4 on axes 2, 3 for (b = g01, binary digits k of axes 4, 5)
+            const int op = tid >> 6, k = (tid >> 4) & 3, g01 = tid & 15;
+            const T* b = B + op * 256 + g01 * 16;
+            const T x[4] = {b[(0 + k) ^ g01], b[(4 + k) ^ g01], b[(8 + k) ^ g01], b[(12 + k) ^ g01]};
+            T y[16];
+            f4_two(x, y);
+            T* c = C + op * 1024 + k * 256 + g01 * 16;
+#pragma unroll
+            for (int e = 0; e < 16; ++e) c[e ^ g01] = y[e];
+        }
+        __syncthreads();
+        {
+            // thread (b, c): F4 on axes 4, 5, the product, G4 on axes 5, 4
+            const int bb = tid >> 4, cc = tid & 15;
+            T x[3][4];
+#pragma unroll
+            for (int op = 0; op < 3; ++op)
+#pragma unroll
+                for (int k = 0; k < 4; ++k) x[op][k] = C[op * 1024 + k * 256 + bb * 16 + (cc ^ bb)];
+            __syncthreads();  // P overwrites C
+            T prod[16];
+            f4_two(x[0], prod);
+#pragma unroll
+            for (int op = 1; op < 3; ++op) {
+                T f[16];
+                f4_two(x[op], f);
+#pragma unroll
+                for (int e = 0; e < 16; ++e) prod[e] = prod[e] * f[e];
+            }
+            g4_two(prod);
+#pragma unroll
+            for (int aa = 0; aa < 16; ++aa) P[aa * 256 + (bb ^ (cc & 1)) * 16 + (cc ^ aa)] = prod[aa];
+        }
+        __syncthreads();
+        {
+            // thread (a, b): G4 on axes 3, 2
+            const int aa = tid & 15, bb = tid >> 4;
+            T q[16];
+#pragma unroll
+            for (int cc = 0; cc < 16; ++cc) q[cc] = P[aa * 256 + (bb ^ (cc & 1)) * 16 + (cc ^ aa)];
+            g4_two(q);
+#pragma unroll
+            for (int cc = 0; cc < 16; ++cc)
+                if (has_mid_digit(cc, 2)) P[aa * 256 + (bb ^ (cc & 1)) * 16 + (cc ^ aa)] = q[cc];
+        }
+        __syncthreads();
+        {
+            // thread (a, c): G4 on axes 1, 0 and the stores
+            const int aa = tid & 15, cc = tid >> 4;
+            T q[16];
+#pragma unroll
+            for (int bb = 0; bb < 16; ++bb) q[bb] = P[aa * 256 + (bb ^ (cc & 1)) * 16 + (cc ^ aa)];
+            g4_two(q);
+            T* zr = z + item * z_bs + (uint64_t)o * 4096 + tid;
+#pragma unroll
+            for (int bb = 0; bb < 16; ++bb) zr[bb * 256] = q[bb];
+        }
+    }
+}
+
+// Inner axes per fused tile (k_s3_tile6 for six; fewer only when D < 6)
+int fused_depth(int D) { return D < 6 ? D : 6; }
 
 struct S3Plan {
     int D = 0, K = 0, p = 0;
     uint64_t n2 = 0, n4 = 0;
     uint64_t stage = 0;  // elements of one forward staging buffer per operand and item
-    std::vector<int> groups;  // outer axes per group, ascending from axis 0
+    std::vector<int> groups;      // forward: outer axes per group, ascending from axis 0
+    std::vector<int> inv_groups;  // inverse: p mod 4 axes first, then groups of 4
 };
 
 S3Plan make_s3_plan(int D, size_t es)
@@ -389,6 +595,8 @@ S3Plan make_s3_plan(int D, size_t es)
         P.groups.push_back(m);
         left -= m;
     }
+    if (P.p % 4) P.inv_groups.push_back(P.p % 4);
+    for (int i = 0; i < P.p / 4; ++i) P.inv_groups.push_back(4);
     // intermediate after a outer axes: 4^a 2^(D-a) = 2^(D+a) elements
     P.stage = P.p > 0 ? (1ull << (D + P.p)) : 0;
     return P;
@@ -415,6 +623,16 @@ void launch_inv(T* z, uint64_t z_bs, uint64_t n_cols, uint32_t log2L, int batch,
     k_s3_inv<T, M><<<grid, S3_NT, 0, s>>>(z, z_bs, n_cols, log2L);
 }
 
+template <typename T>
+void launch_inv4(T* z, uint64_t z_bs, uint64_t n_cols, uint32_t log2L, int batch, hipStream_t s)
+{
+    const uint32_t tiles_per_hi = (uint32_t)((1ull << log2L) / 64);
+    const uint32_t n_tiles = (uint32_t)(n_cols / 64);
+    dim3 grid(n_tiles, batch, 1);
+    LaunchScope scope(s, (double)batch * n_cols * (256.0 + 240.0) * sizeof(T), "s3_inv<%s,M=4>", tname<T>());
+    k_s3_inv4w<T><<<grid, S3_NT, 0, s>>>(z, z_bs, n_tiles, tiles_per_hi, log2L);
+}
+
 template <typename T, int K>
 void launch_fused(const T* r0, const T* r1, const T* r2, T* z, uint64_t r_bs, uint64_t z_bs, uint32_t n_tiles,
                   int batch, int cus, hipStream_t s)
@@ -422,7 +640,9 @@ void launch_fused(const T* r0, const T* r1, const T* r2, T* z, uint64_t r_bs, ui
     dim3 grid(tile_grid(n_tiles, cus, 0), batch, 1);
     LaunchScope scope(s, (double)batch * n_tiles * (3.0 * (1 << K) + (1 << (2 * K))) * sizeof(T),
                       "s3_fused<%s,K=%d>", tname<T>(), K);
-    if constexpr (K >= 2)
+    if constexpr (K == 6)
+        k_s3_tile6<T><<<grid, S3_NT, 0, s>>>(r0, r1, r2, z, r_bs, z_bs, n_tiles);
+    else if constexpr (K >= 2)
         k_s3_fused_r<T, K><<<grid, S3_NT, 0, s>>>(r0, r1, r2, z, r_bs, z_bs, n_tiles);
     else
         k_s3_fused<T, K><<<grid, S3_NT, 0, s>>>(r0, r1, r2, z, r_bs, z_bs, n_tiles);
@@ -464,19 +684,21 @@ int run_s3(const S3Plan& P, const T* x1, const T* x2, const T* x3, T* z, int bat
         case 3: launch_fused<T, 3>(c0, c1, c2, z, c_bs, P.n4, n_tiles, batch, cus, s); break;
         case 4: launch_fused<T, 4>(c0, c1, c2, z, c_bs, P.n4, n_tiles, batch, cus, s); break;
         case 5: launch_fused<T, 5>(c0, c1, c2, z, c_bs, P.n4, n_tiles, batch, cus, s); break;
+        case 6: launch_fused<T, 6>(c0, c1, c2, z, c_bs, P.n4, n_tiles, batch, cus, s); break;
         default: return fail(HC_ERR_UNSUPPORTED, "no three-operand tile of %d axes", P.K);
     }
     // outer inverse: groups descending from the innermost outer axis
     int top = P.p;
-    for (int gi = (int)P.groups.size() - 1; gi >= 0; --gi) {
-        const int M = P.groups[gi];
+    for (int gi = (int)P.inv_groups.size() - 1; gi >= 0; --gi) {
+        const int M = P.inv_groups[gi];
         const int a0 = top - M;
         const uint32_t log2L = (uint32_t)(2 * (D - top));
         const uint64_t n_cols = (1ull << (2 * a0)) << log2L;
         switch (M) {
             case 1: launch_inv<T, 1>(z, P.n4, n_cols, log2L, batch, s); break;
             case 2: launch_inv<T, 2>(z, P.n4, n_cols, log2L, batch, s); break;
-            default: launch_inv<T, 3>(z, P.n4, n_cols, log2L, batch, s); break;
+            case 3: launch_inv<T, 3>(z, P.n4, n_cols, log2L, batch, s); break;
+            default: launch_inv4<T>(z, P.n4, n_cols, log2L, batch, s); break;
         }
         top = a0;
     }

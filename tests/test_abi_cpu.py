@@ -212,11 +212,11 @@ def test_sum3_validation():
     x1, x2, x3, z, ws = FAKE, FAKE + (1 << 22), FAKE + (1 << 23), FAKE + (1 << 26), FAKE + (1 << 34)
     f = _abi.hc_sum3_batch
     big = 1 << 30
-    # workspace: six staging copies of 4^p 2^K entries per item (K = 5),
-    # none when everything fits one tile
-    assert _abi.hc_sum3_workspace_bytes(5, _abi.HC_F64, 1) == 0
-    assert _abi.hc_sum3_workspace_bytes(10, _abi.HC_F64, 2) == 2 * 6 * (1 << 15) * 8
-    assert _abi.hc_sum3_workspace_bytes(10, _abi.HC_F32, 1) == 6 * (1 << 15) * 4
+    # workspace: six staging copies of 4^p 2^K entries per item (K = 6 inner
+    # axes, p = D - K), none when everything fits one tile
+    assert _abi.hc_sum3_workspace_bytes(6, _abi.HC_F64, 1) == 0
+    assert _abi.hc_sum3_workspace_bytes(10, _abi.HC_F64, 2) == 2 * 6 * (1 << 14) * 8
+    assert _abi.hc_sum3_workspace_bytes(10, _abi.HC_F32, 1) == 6 * (1 << 14) * 4
     assert _abi.hc_sum3_workspace_bytes(17, _abi.HC_F64, 1) == _abi.SIZE_MAX
     assert _abi.hc_sum3_workspace_bytes(8, 9, 1) == _abi.SIZE_MAX
     assert f(0, x2, x3, z, 8, 0, 1, ws, big, 0) == 1              # null input
