@@ -44,8 +44,11 @@ def run(xs):
     return hc.sum3(*(on_gpu(x) for x in xs))
 
 
+# D < 6: one tile of D axes; D >= 6: six-axis tiles, then p = D - 6 outer axes
+# as p mod 4 axes in registers and groups of four (D = 10: one group of four
+# alone; D = 13: 3 + 4)
 @pytest.mark.parametrize("dtype", DTYPES)
-@pytest.mark.parametrize("D", [0, 1, 2, 3, 5, 6, 7, 9, 11, 12])
+@pytest.mark.parametrize("D", [0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13])
 def test_sum3_matches_oracle_method(dtype, D):
     xs = triple(D, dtype, 1)
     say(f"D={D} {np.dtype(dtype).name}")
@@ -63,8 +66,8 @@ def test_sum3_int64_matches_definition(D):
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
-def test_sum3_batch_and_inputs_unchanged(dtype):
-    D, B = 9, 5
+@pytest.mark.parametrize("D,B", [(9, 5), (11, 3)])
+def test_sum3_batch_and_inputs_unchanged(dtype, D, B):
     xs = triple(D, dtype, 3, batch=B)
     t = [on_gpu(x) for x in xs]
     copies = [a.clone() for a in t]
