@@ -30,9 +30,10 @@
 //                   contiguous 4^K row of z, every step on two axes held
 //                   in registers                                 (k_s3_tile6)
 //                   (D < 6: one tile of D axes,      k_s3_fused_r / k_s3_fused)
-//   outer inverse   G4 on axes p-1..0 in place: p mod 4 axes in registers
-//                   (k_s3_inv), then groups of 4: three axes in registers,
-//                   the fourth across the workgroup's waves    (k_s3_inv4w)
+//   outer inverse   G4 on axes p-1..0 in place: groups of 4 from axis p-1
+//                   down, three axes in registers and the fourth across the
+//                   workgroup's waves                          (k_s3_inv4w),
+//                   then axes p mod 4 - 1 .. 0 in registers      (k_s3_inv)
 #include "hc.h"
 
 #include <hip/hip_runtime.h>
