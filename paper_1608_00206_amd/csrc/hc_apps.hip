@@ -239,10 +239,7 @@ struct RootCoef {
 // below), eps = V / A - 1 (V - A is exact, |eps| < 1e-3), and
 // V^(1/p) = a (1 + eps)^(1/p), the series cut after eps^4.  The result is
 // within 2 u of the exact root, with a margin of 10x on the seed's error.
-// POW2: p = 2^log2p, so that a^p is log2p squarings (the same products, in
-// the same order, as the binary powering below gives for such p).
-template <bool POW2>
-__device__ __forceinline__ double root_int(double v, int p, int log2p, const RootCoef& rc)
+__device__ __forceinline__ double root_int(double v, int p, const RootCoef& rc)
 {
     int e;
     const double m = frexp(v, &e);
@@ -250,13 +247,7 @@ __device__ __forceinline__ double root_int(double v, int p, int log2p, const Roo
     const int rem = e - n * p;
     const float t = ((float)rem + __builtin_amdgcn_logf((float)m)) * rc.inv_pf;
     const double a = (double)__builtin_amdgcn_exp2f(t);
-    double A;
-    if constexpr (POW2) {
-        A = a;
-        for (int k = 0; k < log2p; ++k) A *= A;
-    } else {
-        A = int_pow<double>(a, p);
-    }
+    const double A = int_pow<double>(a, p);
     const double V = ldexp(m, rem);
     double q = __builtin_amdgcn_rcp(A);
     q = fma(q, fma(-A, q, 1.0), q);
@@ -265,26 +256,56 @@ __device__ __forceinline__ double root_int(double v, int p, int log2p, const Roo
     return ldexp(fma(a, P, a), n);
 }
 
-// How k_root takes the root: p = 1 needs none; integer p in
-// [2, ROOT_INT_MAX] take root_int (in float64 for both types; powers of two
-// with the squaring loop, the same products); other p take
-// exp(log(v) / p), whose relative error is a few ulps times
-// 1 + |ln v| / p.  Either error is far below the estimate's own 2^(s/p) bias.
+// v^(1/p) for finite v > 0 and p = 2^L, L <= ROOT_POW2_MAX, in float64: the
+// steps of root_int with the exponent split by shifts (n = floor((e + p/2) /
+// p), |rem| <= p/2), the L squarings unrolled, and the series cut after
+// eps^2.  The seed's error (t within 2^-24.8 absolute, a within 2^-22.5
+// relative) bounds |eps| by p 2^-22.5 <= 2^-17.5, so the dropped c2 eps^3 +
+// c3 eps^4 stay below u / 60 and the result within 2 u of the exact root.
+constexpr int ROOT_POW2_MAX = 5;
+
+template <int L>
+__device__ __forceinline__ double root_pow2(double v, const RootCoef& rc)
+{
+    constexpr int p = 1 << L;
+    int e;
+    const double m = frexp(v, &e);
+    const int n = (e + p / 2) >> L;
+    const int rem = e - n * p;
+    const float t = ((float)rem + __builtin_amdgcn_logf((float)m)) * (1.0f / (float)p);
+    const double a = (double)__builtin_amdgcn_exp2f(t);
+    double A = a;
+#pragma unroll
+    for (int k = 0; k < L; ++k) A *= A;
+    const double V = ldexp(m, rem);
+    double q = __builtin_amdgcn_rcp(A);
+    q = fma(q, fma(-A, q, 1.0), q);
+    const double eps = (V - A) * q;
+    const double P = eps * (rc.c[0] + eps * rc.c[1]);
+    return ldexp(fma(a, P, a), n);
+}
+
+// How k_root takes the root: p = 1 needs none; p = 2, 4, ..., 2^ROOT_POW2_MAX
+// take root_pow2 (mode ROOT_POW2 + L); other integer p in [2, ROOT_INT_MAX]
+// take root_int (in float64 for both types; larger powers of two with the
+// squaring loop, the same products); other p take exp(log(v) / p), whose
+// relative error is a few ulps times 1 + |ln v| / p.  Every error is far below
+// the estimate's own 2^(s/p) bias.
 enum RootMode { ROOT_NONE = 0, ROOT_INT = 1, ROOT_EXPLOG = 2, ROOT_POW2 = 3 };
 
 // mx my max(v, 0)^(1/p) for one output (s = mx my), optionally rounded.
-// The root is taken on every lane (of 1 where v <= 0) and the result
-// selected, so that no lane waits for a branch around the arithmetic.
+// The root is taken on every lane and the result selected (0 where v <= 0 or
+// v is NaN, whose root arithmetic gives NaN), so that no lane waits for a
+// branch around the arithmetic.
 template <typename T, int MODE>
 __device__ __forceinline__ T root_value(T v, T s, T inv_p, int ip, const RootCoef& rc, int round)
 {
     const bool pos = v > T(0);
-    const T vv = pos ? v : T(1);
     T w;
-    if constexpr (MODE == ROOT_NONE) w = vv;
-    else if constexpr (MODE == ROOT_INT) w = (T)root_int<false>((double)vv, ip, rc.log2p, rc);
-    else if constexpr (MODE == ROOT_POW2) w = (T)root_int<true>((double)vv, ip, rc.log2p, rc);
-    else w = exp_t<T>(log_t<T>(vv) * inv_p);
+    if constexpr (MODE == ROOT_NONE) w = v;
+    else if constexpr (MODE == ROOT_INT) w = (T)root_int((double)v, ip, rc);
+    else if constexpr (MODE > ROOT_POW2) w = (T)root_pow2<MODE - ROOT_POW2>((double)v, rc);
+    else w = exp_t<T>(log_t<T>(v) * inv_p);
     const T sw = s * w;
     T r = pos ? sw : T(0);
     if (round) r = rint(r);
@@ -419,26 +440,30 @@ static int maxconv_t(const T* x, const T* y, T* z, int D, int batch, double p, b
     const bool pow2 = ip >= 2 && (1 << coef.log2p) == ip;
     const T inv_p = (T)c1;
     const int rnd = round ? 1 : 0;
-    const int mode = p == 1 ? ROOT_NONE : (pow2 ? ROOT_POW2 : (ip ? ROOT_INT : ROOT_EXPLOG));
+    const int mode = p == 1 ? ROOT_NONE
+                            : (pow2 && coef.log2p <= ROOT_POW2_MAX ? ROOT_POW2 + coef.log2p
+                                                                   : (ip ? ROOT_INT : ROOT_EXPLOG));
     // the root runs as the epilogue of the convolution's last inverse pass
     // where that pass has an epilogue kernel, else as its own kernel
     const RootEpilogue<T, ROOT_NONE> e_none{scales, batch, inv_p, ip, coef, rnd};
     const RootEpilogue<T, ROOT_INT> e_int{scales, batch, inv_p, ip, coef, rnd};
-    const RootEpilogue<T, ROOT_POW2> e_pow2{scales, batch, inv_p, ip, coef, rnd};
     const RootEpilogue<T, ROOT_EXPLOG> e_explog{scales, batch, inv_p, ip, coef, rnd};
+    const RootEpilogue<T, ROOT_POW2 + 1> e_p1{scales, batch, inv_p, ip, coef, rnd};
+    const RootEpilogue<T, ROOT_POW2 + 2> e_p2{scales, batch, inv_p, ip, coef, rnd};
+    const RootEpilogue<T, ROOT_POW2 + 3> e_p3{scales, batch, inv_p, ip, coef, rnd};
+    const RootEpilogue<T, ROOT_POW2 + 4> e_p4{scales, batch, inv_p, ip, coef, rnd};
+    const RootEpilogue<T, ROOT_POW2 + 5> e_p5{scales, batch, inv_p, ip, coef, rnd};
+    static_assert(ROOT_POW2_MAX == 5, "one epilogue per power of two");
     LastPass last;
-    if (mode == ROOT_NONE) {
-        last.launch = launch_root_pass<T, ROOT_NONE>;
-        last.ctx = &e_none;
-    } else if (mode == ROOT_INT) {
-        last.launch = launch_root_pass<T, ROOT_INT>;
-        last.ctx = &e_int;
-    } else if (mode == ROOT_POW2) {
-        last.launch = launch_root_pass<T, ROOT_POW2>;
-        last.ctx = &e_pow2;
-    } else {
-        last.launch = launch_root_pass<T, ROOT_EXPLOG>;
-        last.ctx = &e_explog;
+    switch (mode) {
+        case ROOT_NONE: last.launch = launch_root_pass<T, ROOT_NONE>; last.ctx = &e_none; break;
+        case ROOT_INT: last.launch = launch_root_pass<T, ROOT_INT>; last.ctx = &e_int; break;
+        case ROOT_POW2 + 1: last.launch = launch_root_pass<T, ROOT_POW2 + 1>; last.ctx = &e_p1; break;
+        case ROOT_POW2 + 2: last.launch = launch_root_pass<T, ROOT_POW2 + 2>; last.ctx = &e_p2; break;
+        case ROOT_POW2 + 3: last.launch = launch_root_pass<T, ROOT_POW2 + 3>; last.ctx = &e_p3; break;
+        case ROOT_POW2 + 4: last.launch = launch_root_pass<T, ROOT_POW2 + 4>; last.ctx = &e_p4; break;
+        case ROOT_POW2 + 5: last.launch = launch_root_pass<T, ROOT_POW2 + 5>; last.ctx = &e_p5; break;
+        default: last.launch = launch_root_pass<T, ROOT_EXPLOG>; last.ctx = &e_explog; break;
     }
     const int rc = convolve_batch_last(xp, yp, z, D, sizeof(T) == 4 ? HC_F32 : HC_F64, batch, ws + sc_b + 2 * op_b,
                                        ws_bytes - sc_b - 2 * op_b, s, separate_root ? nullptr : &last);
@@ -446,10 +471,18 @@ static int maxconv_t(const T* x, const T* y, T* z, int D, int batch, double p, b
     if (!last.taken) {
         LaunchScope scope(s, 2.0 * batch * n3 * sizeof(T), "root<%s>", tname<T>());
         const dim3 grid((uint32_t)((n3 + ROOT_SPAN - 1) / ROOT_SPAN), batch, 1);
-        if (mode == ROOT_NONE) k_root<T, ROOT_NONE><<<grid, APP_NT, 0, s>>>(z, scales, n3, inv_p, ip, coef, rnd);
-        else if (mode == ROOT_INT) k_root<T, ROOT_INT><<<grid, APP_NT, 0, s>>>(z, scales, n3, inv_p, ip, coef, rnd);
-        else if (mode == ROOT_POW2) k_root<T, ROOT_POW2><<<grid, APP_NT, 0, s>>>(z, scales, n3, inv_p, ip, coef, rnd);
-        else k_root<T, ROOT_EXPLOG><<<grid, APP_NT, 0, s>>>(z, scales, n3, inv_p, ip, coef, rnd);
+#define HC_ROOT_K(M) k_root<T, M><<<grid, APP_NT, 0, s>>>(z, scales, n3, inv_p, ip, coef, rnd)
+        switch (mode) {
+            case ROOT_NONE: HC_ROOT_K(ROOT_NONE); break;
+            case ROOT_INT: HC_ROOT_K(ROOT_INT); break;
+            case ROOT_POW2 + 1: HC_ROOT_K(ROOT_POW2 + 1); break;
+            case ROOT_POW2 + 2: HC_ROOT_K(ROOT_POW2 + 2); break;
+            case ROOT_POW2 + 3: HC_ROOT_K(ROOT_POW2 + 3); break;
+            case ROOT_POW2 + 4: HC_ROOT_K(ROOT_POW2 + 4); break;
+            case ROOT_POW2 + 5: HC_ROOT_K(ROOT_POW2 + 5); break;
+            default: HC_ROOT_K(ROOT_EXPLOG); break;
+        }
+#undef HC_ROOT_K
     }
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "max-convolution launch");

@@ -242,7 +242,7 @@ def test_maxconv_rounding_exact_where_certified(R, D, p):
 
 
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
-@pytest.mark.parametrize("p", [2.0, 3.0, 32.0, 1000.0, 1024.0, 7.5, 1025.0])
+@pytest.mark.parametrize("p", [2.0, 3.0, 4.0, 8.0, 16.0, 32.0, 64.0, 1000.0, 1024.0, 7.5, 1025.0])
 def test_maxconv_root_accuracy_over_wide_range(dtype, p):
     """The root alone, over powered values spanning the dtype's normal range.
     With x = [a, 1], y = [b, 1] and 0 < a, b < 1 the maxima are 1, output 0
@@ -250,8 +250,9 @@ def test_maxconv_root_accuracy_over_wide_range(dtype, p):
     (a^p b^p)^(1/p) = a b up to the two powers' and the product's rounding
     (at most 3 u before the root, 3 u / p after it) and the root's own
     error: at most 2 u for integer p up to 1024 (float64 polishing of a
-    float seed, float64 for both dtypes), a few u times 1 + |ln z'| / p for
-    other p (exp(log(z') / p))."""
+    float seed, float64 for both dtypes; p = 2 ... 32 by the short series of
+    the power-of-two form, 64 and 1024 by the general one), a few u times
+    1 + |ln z'| / p for other p (exp(log(z') / p))."""
     g = np.random.default_rng([hc_inputs.SEED, 97, int(p * 2)])
     B = 4096
     fin = np.finfo(dtype)
