@@ -201,6 +201,8 @@ __global__ __launch_bounds__(S3_NT) void k_s3_inv4w(T* __restrict__ z, uint64_t 
         for (int t = 0; t < 64; ++t) v[t] = buf_load<T>(row_rsrc(rp + t * row, SEG), off);
     }
     g4_group<T, 3>(v);
+    // the stores' resources are built from an opaque copy of the base, so
+    // that the loads' 64 resources are not kept live in scalar registers
     char* wbase = tbase;
     asm volatile("" : "+s"(wbase));
 #pragma unroll
