@@ -23,6 +23,7 @@
 // root of the p-norm, which runs as the epilogue of the convolution's last
 // inverse pass where that pass has an epilogue kernel, else in place on z.
 #include <cmath>
+#include <type_traits>
 
 #include "hc.h"
 #include "hc_internal.hpp"
@@ -258,15 +259,19 @@ __device__ __forceinline__ double root_int(double v, int p, const RootCoef& rc)
 
 // v^(1/p) for finite v > 0 and p = 2^L, L <= ROOT_POW2_MAX, in float64: the
 // steps of root_int with the exponent split by shifts (n = floor((e + p/2) /
-// p), |rem| <= p/2), the L squarings unrolled, and the series cut after
-// eps^2.  The seed's error (t within 2^-24.8 absolute, a within 2^-22.5
-// relative) bounds |eps| by p 2^-22.5 <= 2^-17.5, so the dropped c2 eps^3 +
-// c3 eps^4 stay below u / 60 and the result within 2 u of the exact root.
-constexpr int ROOT_POW2_MAX = 5;
+// p), |rem| <= p/2) and the L squarings unrolled.  The seed's error (t
+// within 2^-24.8 absolute, a within 2^-22.5 relative) bounds |eps| by
+// p 2^-22.5; for p <= 32 that is 2^-17.5, so the series stops after eps^2
+// (the dropped c2 eps^3 + c3 eps^4 stay below u / 60); larger p keep the
+// terms to eps^4, as root_int does.  Either way the result is within 2 u of
+// the exact root.
+constexpr int ROOT_POW2_MAX = 10;  // 2^10 = ROOT_INT_MAX
+constexpr int ROOT_SHORT_SERIES_MAX = 5;
 
 template <int L>
 __device__ __forceinline__ double root_pow2(double v, const RootCoef& rc)
 {
+    static_assert(L >= 1 && L <= ROOT_POW2_MAX && (1 << ROOT_POW2_MAX) == ROOT_INT_MAX, "p = 2 ... ROOT_INT_MAX");
     constexpr int p = 1 << L;
     int e;
     const double m = frexp(v, &e);
@@ -281,16 +286,17 @@ __device__ __forceinline__ double root_pow2(double v, const RootCoef& rc)
     double q = __builtin_amdgcn_rcp(A);
     q = fma(q, fma(-A, q, 1.0), q);
     const double eps = (V - A) * q;
-    const double P = eps * (rc.c[0] + eps * rc.c[1]);
+    double P;
+    if constexpr (L <= ROOT_SHORT_SERIES_MAX) P = eps * (rc.c[0] + eps * rc.c[1]);
+    else P = eps * (rc.c[0] + eps * (rc.c[1] + eps * (rc.c[2] + eps * rc.c[3])));
     return ldexp(fma(a, P, a), n);
 }
 
 // How k_root takes the root: p = 1 needs none; p = 2, 4, ..., 2^ROOT_POW2_MAX
 // take root_pow2 (mode ROOT_POW2 + L); other integer p in [2, ROOT_INT_MAX]
-// take root_int (in float64 for both types; larger powers of two with the
-// squaring loop, the same products); other p take exp(log(v) / p), whose
-// relative error is a few ulps times 1 + |ln v| / p.  Every error is far below
-// the estimate's own 2^(s/p) bias.
+// take root_int (in float64 for both types); other p take exp(log(v) / p),
+// whose relative error is a few ulps times 1 + |ln v| / p.  Every error is
+// far below the estimate's own 2^(s/p) bias.
 enum RootMode { ROOT_NONE = 0, ROOT_INT = 1, ROOT_EXPLOG = 2, ROOT_POW2 = 3 };
 
 // mx my max(v, 0)^(1/p) for one output (s = mx my), optionally rounded.
@@ -445,45 +451,42 @@ static int maxconv_t(const T* x, const T* y, T* z, int D, int batch, double p, b
                                                                    : (ip ? ROOT_INT : ROOT_EXPLOG));
     // the root runs as the epilogue of the convolution's last inverse pass
     // where that pass has an epilogue kernel, else as its own kernel
-    const RootEpilogue<T, ROOT_NONE> e_none{scales, batch, inv_p, ip, coef, rnd};
-    const RootEpilogue<T, ROOT_INT> e_int{scales, batch, inv_p, ip, coef, rnd};
-    const RootEpilogue<T, ROOT_EXPLOG> e_explog{scales, batch, inv_p, ip, coef, rnd};
-    const RootEpilogue<T, ROOT_POW2 + 1> e_p1{scales, batch, inv_p, ip, coef, rnd};
-    const RootEpilogue<T, ROOT_POW2 + 2> e_p2{scales, batch, inv_p, ip, coef, rnd};
-    const RootEpilogue<T, ROOT_POW2 + 3> e_p3{scales, batch, inv_p, ip, coef, rnd};
-    const RootEpilogue<T, ROOT_POW2 + 4> e_p4{scales, batch, inv_p, ip, coef, rnd};
-    const RootEpilogue<T, ROOT_POW2 + 5> e_p5{scales, batch, inv_p, ip, coef, rnd};
-    static_assert(ROOT_POW2_MAX == 5, "one epilogue per power of two");
-    LastPass last;
-    switch (mode) {
-        case ROOT_NONE: last.launch = launch_root_pass<T, ROOT_NONE>; last.ctx = &e_none; break;
-        case ROOT_INT: last.launch = launch_root_pass<T, ROOT_INT>; last.ctx = &e_int; break;
-        case ROOT_POW2 + 1: last.launch = launch_root_pass<T, ROOT_POW2 + 1>; last.ctx = &e_p1; break;
-        case ROOT_POW2 + 2: last.launch = launch_root_pass<T, ROOT_POW2 + 2>; last.ctx = &e_p2; break;
-        case ROOT_POW2 + 3: last.launch = launch_root_pass<T, ROOT_POW2 + 3>; last.ctx = &e_p3; break;
-        case ROOT_POW2 + 4: last.launch = launch_root_pass<T, ROOT_POW2 + 4>; last.ctx = &e_p4; break;
-        case ROOT_POW2 + 5: last.launch = launch_root_pass<T, ROOT_POW2 + 5>; last.ctx = &e_p5; break;
-        default: last.launch = launch_root_pass<T, ROOT_EXPLOG>; last.ctx = &e_explog; break;
-    }
-    const int rc = convolve_batch_last(xp, yp, z, D, sizeof(T) == 4 ? HC_F32 : HC_F64, batch, ws + sc_b + 2 * op_b,
-                                       ws_bytes - sc_b - 2 * op_b, s, separate_root ? nullptr : &last);
-    if (rc != HC_OK) return rc;
-    if (!last.taken) {
-        LaunchScope scope(s, 2.0 * batch * n3 * sizeof(T), "root<%s>", tname<T>());
-        const dim3 grid((uint32_t)((n3 + ROOT_SPAN - 1) / ROOT_SPAN), batch, 1);
-#define HC_ROOT_K(M) k_root<T, M><<<grid, APP_NT, 0, s>>>(z, scales, n3, inv_p, ip, coef, rnd)
-        switch (mode) {
-            case ROOT_NONE: HC_ROOT_K(ROOT_NONE); break;
-            case ROOT_INT: HC_ROOT_K(ROOT_INT); break;
-            case ROOT_POW2 + 1: HC_ROOT_K(ROOT_POW2 + 1); break;
-            case ROOT_POW2 + 2: HC_ROOT_K(ROOT_POW2 + 2); break;
-            case ROOT_POW2 + 3: HC_ROOT_K(ROOT_POW2 + 3); break;
-            case ROOT_POW2 + 4: HC_ROOT_K(ROOT_POW2 + 4); break;
-            case ROOT_POW2 + 5: HC_ROOT_K(ROOT_POW2 + 5); break;
-            default: HC_ROOT_K(ROOT_EXPLOG); break;
+    auto run = [&](auto mode_c) -> int {
+        constexpr int M = decltype(mode_c)::value;
+        const RootEpilogue<T, M> epi{scales, batch, inv_p, ip, coef, rnd};
+        LastPass last;
+        last.launch = launch_root_pass<T, M>;
+        last.ctx = &epi;
+        const int rc = convolve_batch_last(xp, yp, z, D, sizeof(T) == 4 ? HC_F32 : HC_F64, batch,
+                                           ws + sc_b + 2 * op_b, ws_bytes - sc_b - 2 * op_b, s,
+                                           separate_root ? nullptr : &last);
+        if (rc != HC_OK) return rc;
+        if (!last.taken) {
+            LaunchScope scope(s, 2.0 * batch * n3 * sizeof(T), "root<%s>", tname<T>());
+            const dim3 grid((uint32_t)((n3 + ROOT_SPAN - 1) / ROOT_SPAN), batch, 1);
+            k_root<T, M><<<grid, APP_NT, 0, s>>>(z, scales, n3, inv_p, ip, coef, rnd);
         }
-#undef HC_ROOT_K
+        return HC_OK;
+    };
+    using std::integral_constant;
+    int rc;
+    switch (mode) {
+        case ROOT_NONE: rc = run(integral_constant<int, ROOT_NONE>{}); break;
+        case ROOT_INT: rc = run(integral_constant<int, ROOT_INT>{}); break;
+        case ROOT_POW2 + 1: rc = run(integral_constant<int, ROOT_POW2 + 1>{}); break;
+        case ROOT_POW2 + 2: rc = run(integral_constant<int, ROOT_POW2 + 2>{}); break;
+        case ROOT_POW2 + 3: rc = run(integral_constant<int, ROOT_POW2 + 3>{}); break;
+        case ROOT_POW2 + 4: rc = run(integral_constant<int, ROOT_POW2 + 4>{}); break;
+        case ROOT_POW2 + 5: rc = run(integral_constant<int, ROOT_POW2 + 5>{}); break;
+        case ROOT_POW2 + 6: rc = run(integral_constant<int, ROOT_POW2 + 6>{}); break;
+        case ROOT_POW2 + 7: rc = run(integral_constant<int, ROOT_POW2 + 7>{}); break;
+        case ROOT_POW2 + 8: rc = run(integral_constant<int, ROOT_POW2 + 8>{}); break;
+        case ROOT_POW2 + 9: rc = run(integral_constant<int, ROOT_POW2 + 9>{}); break;
+        case ROOT_POW2 + 10: rc = run(integral_constant<int, ROOT_POW2 + 10>{}); break;
+        default: rc = run(integral_constant<int, ROOT_EXPLOG>{}); break;
     }
+    static_assert(ROOT_POW2_MAX == 10, "one case per power of two");
+    if (rc != HC_OK) return rc;
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "max-convolution launch");
     return HC_OK;
