@@ -126,3 +126,29 @@ def test_sum3_d16_int64_sampled_definition():
     assert total == int(xs[0].sum()) * int(xs[1].sum()) * int(xs[2].sum())
     del z
     torch.cuda.empty_cache()
+
+
+def test_sum3_d16_float64_exact_on_binary_inputs():
+    """D = 16 float64 with inputs in {0, 1}: every forward value is an integer
+    below 2^17, every product below 2^51, and the inverse's halvings divide
+    even integers, so the method is exact in float64 and every one of the
+    4^16 outputs must equal the int64 result of the same inputs (itself
+    checked against the definition at sampled indices)."""
+    D = 16
+    g = np.random.default_rng([hc_inputs.SEED, 93])
+    xs = [g.integers(0, 2, 1 << D, dtype=np.int64) for _ in range(3)]
+    say("D=16 float64 on binary inputs: GPU")
+    zf = hc.sum3(*(on_gpu(x.astype(np.float64)) for x in xs))
+    zi = hc.sum3(*(on_gpu(x) for x in xs))
+    torch.cuda.synchronize(DEV)
+    n = zf.numel()
+    step = 1 << 28
+    for a in range(0, n, step):
+        b = min(n, a + step)
+        assert torch.equal(zf[a:b], zi[a:b].to(torch.float64)), f"chunk {a}"
+    ks = np.unique(np.random.default_rng([hc_inputs.SEED, 94]).integers(0, 4 ** D, 256, dtype=np.uint64))
+    got = zf[torch.from_numpy(ks.astype(np.int64)).to(DEV)].cpu().numpy()
+    ref = oracle.sum3_direct_at(*(x.astype(np.float64) for x in xs), ks)
+    assert np.array_equal(got, ref)
+    del zf, zi
+    torch.cuda.empty_cache()
