@@ -32,7 +32,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liboracle.so")
 SOURCES = [os.path.join(_HERE, "hc_oracle.c"), os.path.join(_HERE, "hc_oracle_impl.h"),
-           os.path.join(_HERE, "hc_oracle_sum3.h")]
+           os.path.join(_HERE, "hc_oracle_sum3.h"), os.path.join(_HERE, "hc_oracle_ternary.h")]
 
 CFLAGS = ["-O2", "-std=c11", "-Wall", "-Wextra", "-ffp-contract=off", "-fno-fast-math",
           "-fopenmp", "-fPIC", "-shared"]
@@ -74,7 +74,9 @@ def configure(lib):
                            ("hco_carryfree_naive_", [P, P, ctypes.c_uint64, P]),
                            ("hco_difference_naive_", [P, P, P, I]),
                            ("hco_sum3_naive_", [P, P, P, P, I]),
-                           ("hco_sum3_canonical_", [P, P, P, P, I])):
+                           ("hco_sum3_canonical_", [P, P, P, P, I]),
+                           ("hco_ternary_naive_", [P, P, P, I]),
+                           ("hco_ternary_canonical_", [P, P, P, I])):
             fn = getattr(lib, name + sfx)
             fn.argtypes = args
             fn.restype = I
@@ -104,6 +106,10 @@ def configure(lib):
     lib.hco_sum3_direct_at_f64.restype = None
     lib.hco_sum3_bound_f64.argtypes = [P, P, P, P, I]
     lib.hco_sum3_bound_f64.restype = I
+    lib.hco_ternary_direct_at_f64.argtypes = [P, P, I, P, I64, P]
+    lib.hco_ternary_direct_at_f64.restype = None
+    lib.hco_ternary_bound_f64.argtypes = [P, P, P, I]
+    lib.hco_ternary_bound_f64.restype = I
     return lib
 
 
@@ -359,6 +365,66 @@ def sum3_bound(x1, x2, x3) -> np.ndarray:
     if _load().hco_sum3_bound_f64(_ptr(x1), _ptr(x2), _ptr(x3), _ptr(b), D):
         raise ValueError("sum3_bound: D out of range")
     return b
+
+
+def _ternary_pair(a, b):
+    a, b = _vec(a), _vec(b)
+    if a.dtype != b.dtype or a.size != b.size:
+        raise ValueError("a and b must have the same dtype and size")
+    n = a.size
+    D = 0
+    while 3 ** D < n:
+        D += 1
+    if 3 ** D != n:
+        raise ValueError("length must be a power of 3")
+    return a, b, D, _SFX[a.dtype]
+
+
+def ternary_naive(a, b) -> np.ndarray:
+    """Convolution of two ternary cubes {0,1,2}^D (3^D values each, the
+    layout of the hypercube convolution's output) into 5^D values (base-5
+    digit = sum of the two ternary digits) by its definition, every pair of
+    entries (D <= 8)."""
+    a, b, D, sfx = _ternary_pair(a, b)
+    z = np.empty(5 ** D, dtype=a.dtype)
+    rc = getattr(_load(), "hco_ternary_naive_" + sfx)(_ptr(a), _ptr(b), _ptr(z), D)
+    if rc:
+        raise RuntimeError(f"hco_ternary_naive_{sfx} failed ({rc})")
+    return z
+
+
+def ternary_canonical(a, b) -> np.ndarray:
+    """The same convolution by the six-product per-axis method: forward
+    (a0, a1, a2) -> (a0, a1, a2, a0 + a1, a1 + a2, a0 + a2) on axes 0..D-1,
+    the product, inverse (p0, p1, p2, q01, q12, q02) -> (p0, (q01 - p0) - p1,
+    ((q02 - p0) - p2) + p1, (q12 - p1) - p2, p2) on axes D-1..0 (D <= 10)."""
+    a, b, D, sfx = _ternary_pair(a, b)
+    z = np.empty(5 ** D, dtype=a.dtype)
+    rc = getattr(_load(), "hco_ternary_canonical_" + sfx)(_ptr(a), _ptr(b), _ptr(z), D)
+    if rc:
+        raise RuntimeError(f"hco_ternary_canonical_{sfx} failed ({rc})")
+    return z
+
+
+def ternary_direct_at(a, b, ks) -> np.ndarray:
+    """Definition of the ternary convolution at chosen output indices,
+    compensated long double sums (float64 data)."""
+    a, b, D, _ = _ternary_pair(np.asarray(a, dtype=np.float64), np.asarray(b, dtype=np.float64))
+    ks = np.ascontiguousarray(ks, dtype=np.uint64).reshape(-1)
+    if ks.size and int(ks.max()) >= 5 ** D:
+        raise ValueError("output index out of range")
+    out = np.empty(ks.size, dtype=np.float64)
+    _load().hco_ternary_direct_at_f64(_ptr(a), _ptr(b), D, _ptr(ks), ks.size, _ptr(out))
+    return out
+
+
+def ternary_bound(a, b) -> np.ndarray:
+    """B with |ternary_canonical - exact| <= (5D + 1) u B (D <= 10)."""
+    a, b, D, _ = _ternary_pair(np.asarray(a, dtype=np.float64), np.asarray(b, dtype=np.float64))
+    out = np.empty(5 ** D, dtype=np.float64)
+    if _load().hco_ternary_bound_f64(_ptr(a), _ptr(b), _ptr(out), D):
+        raise ValueError("ternary_bound: D out of range")
+    return out
 
 
 def unit_roundoff(dtype) -> float:

@@ -21,6 +21,10 @@
  *   hco_sum3_naive_*, hco_sum3_canonical_*  distribution of X1 + X2 + X3
  *                    by its definition and by the per-axis method extended
  *                    to three operands (hc_oracle_sum3.h)
+ *   hco_ternary_naive_*, hco_ternary_canonical_*  convolution of two ternary
+ *                    cubes {0,1,2}^D (the distribution of X1 + ... + X4 from
+ *                    two pair sums) by its definition and by the six-product
+ *                    per-axis method (hc_oracle_ternary.h)
  * plus fp64/long double helpers for pins: the max-convolution and its p-norm
  * estimate at single indices, the ternary index map, the direct
  * per-element definition sum, the direct correlation gradient and the
@@ -71,6 +75,7 @@ uint64_t hco_tern(uint64_t i)
 #define HCO_HALF(v) ((v) * 0.5)
 #include "hc_oracle_impl.h"
 #include "hc_oracle_sum3.h"
+#include "hc_oracle_ternary.h"
 #undef ELEM
 #undef SFX
 #undef HCO_HALF
@@ -80,6 +85,7 @@ uint64_t hco_tern(uint64_t i)
 #define HCO_HALF(v) ((v) * 0.5f)
 #include "hc_oracle_impl.h"
 #include "hc_oracle_sum3.h"
+#include "hc_oracle_ternary.h"
 #undef ELEM
 #undef SFX
 #undef HCO_HALF
@@ -89,6 +95,7 @@ uint64_t hco_tern(uint64_t i)
 #define HCO_HALF(v) ((uint64_t)((int64_t)(v) / 2))
 #include "hc_oracle_impl.h"
 #include "hc_oracle_sum3.h"
+#include "hc_oracle_ternary.h"
 #undef ELEM
 #undef SFX
 #undef HCO_HALF
@@ -437,6 +444,114 @@ void hco_sum3_direct_at_f64(const double* x1, const double* x2, const double* x3
         }
         out[r] = (double)(acc.s + acc.c);
     }
+}
+
+/* The convolution of two ternary cubes by its definition at chosen output
+ * indices (base-5 digits), every pair of entries whose digits sum to the
+ * output's, Neumaier-compensated in long double (float64 data). */
+void hco_ternary_direct_at_f64(const double* a, const double* b, int D, const uint64_t* ks, int64_t n,
+                               double* out)
+{
+    for (int64_t r = 0; r < n; ++r) {
+        int digit[64];
+        uint64_t k = ks[r];
+        uint64_t n_terms = 1;
+        for (int d = 0; d < D; ++d) {
+            digit[d] = (int)(k % 5);
+            k /= 5;
+            /* pairs (i, j) in {0,1,2}^2 with i + j = digit: 1, 2, 3, 2, 1 */
+            n_terms *= (uint64_t)(digit[d] <= 2 ? digit[d] + 1 : 5 - digit[d]);
+        }
+        hco_acc acc = {0.0L, 0.0L};
+        for (uint64_t m = 0; m < n_terms; ++m) {
+            uint64_t i = 0, j = 0, w = 1, mm = m;
+            for (int d = 0; d < D; ++d) {
+                const int s = digit[d];
+                const int lo = s <= 2 ? 0 : s - 2;   /* smallest i on this axis */
+                const int cnt = s <= 2 ? s + 1 : 5 - s;
+                const int id = lo + (int)(mm % (uint64_t)cnt);
+                mm /= (uint64_t)cnt;
+                i += (uint64_t)id * w;
+                j += (uint64_t)(s - id) * w;
+                w *= 3;
+            }
+            hco_acc_add(&acc, (long double)a[i] * (long double)b[j]);
+        }
+        out[r] = (double)(acc.s + acc.c);
+    }
+}
+
+/* Magnitude bounding the rounding error of the ternary convolution's
+ * per-axis method (first-order rounding analysis, as for the other bounds):
+ *   B = |U|(T|a| . T|b|),
+ *   T:   (a0, a1, a2) -> (a0, a1, a2, a0 + a1, a1 + a2, a0 + a2)
+ *   |U|: (p0, p1, p2, q01, q12, q02) -> (p0, q01 + p0 + p1,
+ *         q02 + p0 + p2 + p1, q12 + p1 + p2, p2)
+ * with |computed - exact| <= (5D + 1) u B: at most D roundings per forward
+ * value, one per product and three per inverse step.  b receives 5^D
+ * values (D <= 10). */
+int hco_ternary_bound_f64(const double* a, const double* b, double* out, int D)
+{
+    if (D < 0 || D > 10) return 1;
+    const uint64_t n3 = hco_pow3(D);
+    uint64_t n6 = 1, n5 = 1;
+    for (int d = 0; d < D; ++d) { n6 *= 6; n5 *= 5; }
+    double* fa = (double*)malloc(n6 * sizeof(double));
+    double* fb = (double*)malloc(n6 * sizeof(double));
+    double* t = (double*)malloc(n6 * sizeof(double));
+    if (!fa || !fb || !t) { free(fa); free(fb); free(t); return 2; }
+    double* ops[2] = {fa, fb};
+    const double* src[2] = {a, b};
+    for (int o = 0; o < 2; ++o) {
+        /* T on |x|, axes ascending, ping-pong so that the last axis lands in ops[o] */
+        double* cur = (D % 2 == 0) ? ops[o] : t;
+        double* nxt = (D % 2 == 0) ? t : ops[o];
+        for (uint64_t i = 0; i < n3; ++i) cur[i] = fabs(src[o][i]);
+        for (int ax = 0; ax < D; ++ax) {
+            uint64_t n_hi = 1, n_lo = 1;
+            for (int d = 0; d < ax; ++d) n_hi *= 6;
+            for (int d = ax + 1; d < D; ++d) n_lo *= 3;
+            for (uint64_t hi = 0; hi < n_hi; ++hi)
+                for (uint64_t lo = 0; lo < n_lo; ++lo) {
+                    const double a0 = cur[(hi * 3 + 0) * n_lo + lo];
+                    const double a1 = cur[(hi * 3 + 1) * n_lo + lo];
+                    const double a2 = cur[(hi * 3 + 2) * n_lo + lo];
+                    nxt[(hi * 6 + 0) * n_lo + lo] = a0;
+                    nxt[(hi * 6 + 1) * n_lo + lo] = a1;
+                    nxt[(hi * 6 + 2) * n_lo + lo] = a2;
+                    nxt[(hi * 6 + 3) * n_lo + lo] = a0 + a1;
+                    nxt[(hi * 6 + 4) * n_lo + lo] = a1 + a2;
+                    nxt[(hi * 6 + 5) * n_lo + lo] = a0 + a2;
+                }
+            double* s = cur; cur = nxt; nxt = s;
+        }
+    }
+    for (uint64_t k = 0; k < n6; ++k) fa[k] = fa[k] * fb[k];
+    double* cur = fa;
+    double* nxt = t;
+    for (int ax = D - 1; ax >= 0; --ax) {
+        uint64_t n_hi = 1, n_lo = 1;
+        for (int d = 0; d < ax; ++d) n_hi *= 6;
+        for (int d = ax + 1; d < D; ++d) n_lo *= 5;
+        for (uint64_t hi = 0; hi < n_hi; ++hi)
+            for (uint64_t lo = 0; lo < n_lo; ++lo) {
+                const double* p = cur + hi * 6 * n_lo + lo;
+                double* c = nxt + hi * 5 * n_lo + lo;
+                const double p0 = p[0], p1 = p[n_lo], p2 = p[2 * n_lo];
+                const double q01 = p[3 * n_lo], q12 = p[4 * n_lo], q02 = p[5 * n_lo];
+                c[0] = p0;
+                c[n_lo] = q01 + p0 + p1;
+                c[2 * n_lo] = q02 + p0 + p2 + p1;
+                c[3 * n_lo] = q12 + p1 + p2;
+                c[4 * n_lo] = p2;
+            }
+        double* s = cur; cur = nxt; nxt = s;
+    }
+    for (uint64_t k = 0; k < n5; ++k) out[k] = cur[k];
+    free(fa);
+    free(fb);
+    free(t);
+    return 0;
 }
 
 /* Magnitude bounding the rounding error of the three-operand method

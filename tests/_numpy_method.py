@@ -68,3 +68,39 @@ def sum3_per_axis(x1, x2, x3, *, minus_point=True, halve=True, inverse_order="de
         v[:, 2] = s - p0
         Z = v.reshape(-1)
     return Z
+
+
+def ternary_per_axis(a, b, *, forward_order="asc", inverse_order="desc", q02_sign=1, keep_p1=True,
+                     c1_drop_p1=False, slot_swap=False):
+    """numpy transcription of the six-product per-axis method for two ternary
+    cubes with switches that plant mistakes."""
+    n = int(a.size)
+    D = 0
+    while 3 ** D < n:
+        D += 1
+    ops = []
+    axes = list(range(D)) if forward_order == "asc" else list(range(D))[::-1]
+    for X in (a.copy(), b.copy()):
+        shape = [3] * D
+        for ax in axes:
+            v = X.reshape(int(np.prod(shape[:ax], dtype=np.int64)), 3, -1)
+            a0, a1, a2 = v[:, 0], v[:, 1], v[:, 2]
+            s02 = a0 + a2 if q02_sign > 0 else a0 - a2
+            slots = [a0, a1, a2, a0 + a1, a1 + a2, s02]
+            if slot_swap:
+                slots[3], slots[4] = slots[4], slots[3]
+            X = np.stack(slots, axis=1).reshape(-1)
+            shape[ax] = 6
+        ops.append(X)
+    Z = ops[0] * ops[1]
+    shape = [6] * D
+    inv_axes = list(range(D))[::-1] if inverse_order == "desc" else list(range(D))
+    for ax in inv_axes:
+        v = Z.reshape(int(np.prod(shape[:ax], dtype=np.int64)), 6, -1)
+        p0, p1, p2, q01, q12, q02 = (v[:, i] for i in range(6))
+        c1 = (q01 - p0) if c1_drop_p1 else (q01 - p0) - p1
+        c2 = ((q02 - p0) - p2) + p1 if keep_p1 else (q02 - p0) - p2
+        c3 = (q12 - p1) - p2
+        Z = np.stack([p0, c1, c2, c3, p2], axis=1).reshape(-1)
+        shape[ax] = 5
+    return Z
