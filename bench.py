@@ -398,6 +398,26 @@ def run_apps(args, torch, hc, steps=None, warmup=None):
                            "kernels": kernel_table(st, steps)}
     del xs, z, ws
     torch.cuda.empty_cache()
+    # distribution of X1 + X2 + X3 + X4, D = 12: the two pair sums, then
+    # their ternary convolution
+    D = 12
+    xs = [torch.from_numpy(hc_inputs.masses(D, hc_inputs.W_D16, 1, role)).to(dev) for role in range(4)]
+    p12 = torch.empty(3 ** D, dtype=torch.float64, device=dev)
+    p34 = torch.empty(3 ** D, dtype=torch.float64, device=dev)
+    z = torch.empty(5 ** D, dtype=torch.float64, device=dev)
+    ws = torch.empty(max(hc._abi.hc_ternary_workspace_bytes(D, hc._abi.HC_F64, 1), hc.workspace_bytes(D, torch.float64),
+                         1), dtype=torch.uint8, device=dev)
+
+    def sum4_step():
+        hc.convolve(xs[0], xs[1], out=p12, workspace=ws)
+        hc.convolve(xs[2], xs[3], out=p34, workspace=ws)
+        hc.ternary_convolve(p12, p34, out=z, workspace=ws)
+    ms, _, st = time_steps(sum4_step, steps, warmup, torch)
+    log(f"sum of four D={D}: {ms:.3f} ms/step")
+    out["sum4_D12_f64"] = {"D": D, "ms_per_step": round(ms, 4), "output_elems_per_s": round(5 ** D / (ms / 1e3), 1),
+                           "kernels": kernel_table(st, steps)}
+    del xs, p12, p34, z, ws
+    torch.cuda.empty_cache()
     return out
 
 

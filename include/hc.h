@@ -154,6 +154,37 @@ int hc_sum3_batch(const void* x1, const void* x2, const void* x3, void* z, int D
                   void* workspace, size_t workspace_bytes, hipStream_t stream);
 
 /*
+ * Convolution of two ternary cubes {0,1,2}^D x {0,1,2}^D -> {0,...,4}^D, the
+ * next link of a chain of sums (Introduction: sums of multiple probability
+ * mass functions whose axes are Bernoulli variables): with a the output of
+ * hc_convolve for X1, X2 and b that for X3, X4, z is the distribution of
+ * X1 + X2 + X3 + X4:
+ *   z[k] = sum over i, j in {0,1,2}^D with i + j = k of a[i] * b[j],
+ * every digit of k in {0, ..., 4}.  Computed by the Methods section's
+ * Karatsuba identity taken to lines of three: along one axis each operand
+ * is a quadratic, and the quartic product needs six products and no
+ * division:
+ *   forward  (a0, a1, a2) -> (a0, a1, a2, a0 + a1, a1 + a2, a0 + a2)
+ *                                                            axes 0..D-1
+ *   product  a^ * b^                                         elementwise
+ *   inverse  (p0, p1, p2, q01, q12, q02) -> (p0, (q01 - p0) - p1,
+ *            ((q02 - p0) - p2) + p1, (q12 - p1) - p2, p2)    axes D-1..0
+ * each one IEEE operation in this order.  int64 data wraps modulo 2^64
+ * (exact: there is no division).
+ *   a, b        device, batch x 3^D elements each (read only; layout as the
+ *               z of hc_convolve: ternary digit d, weight 3^d, is the
+ *               coordinate on axis D-1-d)
+ *   z           device, batch x 5^D elements (written); base-5 digit d of
+ *               the flat index (weight 5^d) is the coordinate on axis D-1-d
+ *   workspace   hc_ternary_workspace_bytes(D, dtype, batch) bytes
+ * 0 <= D <= 12, 1 <= batch <= 65535.
+ * Errors: as hc_convolve_batch (HC_ERR_D_RANGE above D = 12).
+ */
+size_t hc_ternary_workspace_bytes(int D, int dtype, int batch);  /* (size_t)-1 if invalid */
+int hc_ternary_convolve_batch(const void* a, const void* b, void* z, int D, int dtype, int batch,
+                              void* workspace, size_t workspace_bytes, hipStream_t stream);
+
+/*
  * hc_convolve_batch for callers that cannot allocate device memory (code
  * under HIP graph capture, tight serving loops, harnesses that forbid
  * hipMalloc).  Same operation, arguments, kernels and results (bitwise) as

@@ -297,6 +297,59 @@ def sum3(x1: torch.Tensor, x2: torch.Tensor, x3: torch.Tensor, out: torch.Tensor
     return sum3_batch(x1.view(1, n), x2.view(1, n), x3.view(1, n), out=flat, workspace=workspace).view(-1)
 
 
+def ternary_dim_of(n: int) -> int:
+    D = 0
+    while 3 ** D < n:
+        D += 1
+    if n <= 0 or 3 ** D != n:
+        raise ValueError(f"a ternary cube has 3^D entries, got {n}")
+    return D
+
+
+def ternary_convolve_batch(a: torch.Tensor, b: torch.Tensor, out: torch.Tensor | None = None,
+                           workspace: torch.Tensor | None = None) -> torch.Tensor:
+    """Convolution of two ternary cubes {0,1,2}^D, (B, 3^D) each (the layout
+    of convolve's output), into (B, 5^D): base-5 digit d of an output index
+    is the sum of the two ternary digits on axis D-1-d."""
+    if a.dim() != 2 or a.shape != b.shape:
+        raise ValueError("a and b must both have shape (B, 3^D)")
+    if a.dtype != b.dtype:
+        raise TypeError("a and b must have the same dtype")
+    _check_device(a, b)
+    B, n = a.shape
+    D = ternary_dim_of(n)
+    code = _dtype_code(a)
+    a, b = a.contiguous(), b.contiguous()
+    if out is None:
+        out = torch.empty((B, 5 ** D), dtype=a.dtype, device=a.device)
+    elif out.shape != (B, 5 ** D) or out.dtype != a.dtype or not out.is_contiguous() or out.device != a.device:
+        raise ValueError("out must be a contiguous (B, 5^D) tensor of the input dtype")
+    nbytes = _abi.hc_ternary_workspace_bytes(D, code, B)
+    if nbytes == _abi.SIZE_MAX:
+        raise ValueError("invalid D, dtype or batch for ternary_convolve")
+    ws = _workspace(nbytes, a.device, workspace)
+    _launch(a.device, _abi.hc_ternary_convolve_batch, a.data_ptr(), b.data_ptr(), out.data_ptr(), D, code, B,
+            ws.data_ptr() if ws is not None else 0, nbytes, _stream(a.device))
+    return out
+
+
+def ternary_convolve(a: torch.Tensor, b: torch.Tensor, out: torch.Tensor | None = None,
+                     workspace: torch.Tensor | None = None) -> torch.Tensor:
+    """Single-pair form of ternary_convolve_batch: (3^D,) inputs, (5^D,) output."""
+    if a.dim() != 1:
+        raise ValueError("a and b must be 1-D tensors of length 3^D")
+    n = a.numel()
+    flat = out.view(1, -1) if out is not None else None
+    return ternary_convolve_batch(a.view(1, n), b.view(1, n), out=flat, workspace=workspace).view(-1)
+
+
+def sum4(x1: torch.Tensor, x2: torch.Tensor, x3: torch.Tensor, x4: torch.Tensor) -> torch.Tensor:
+    """Distribution of X1 + X2 + X3 + X4 for four (2^D,) distributions over
+    {0,1}^D: the pair sums by convolve, then their ternary convolution.
+    Returns (5^D,), base-5 digit = the sum of the four coordinates."""
+    return ternary_convolve(convolve(x1, x2), convolve(x3, x4))
+
+
 def difference(x: torch.Tensor, y: torch.Tensor, out: torch.Tensor | None = None,
                workspace: torch.Tensor | None = None) -> torch.Tensor:
     """Single-pair form of difference_batch: (2^D,) inputs, (3^D,) output."""

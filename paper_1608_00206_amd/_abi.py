@@ -77,6 +77,8 @@ SIGNATURES = {
     "hc_maxconv_pnorm_batch": ([_P, _P, _P, _I, _I, _I, ctypes.c_double, ctypes.c_uint, _P, _SZ, _P], _I),
     "hc_sum3_workspace_bytes": ([_I, _I, _I], _SZ),
     "hc_sum3_batch": ([_P, _P, _P, _P, _I, _I, _I, _P, _SZ, _P], _I),
+    "hc_ternary_workspace_bytes": ([_I, _I, _I], _SZ),
+    "hc_ternary_convolve_batch": ([_P, _P, _P, _I, _I, _I, _P, _SZ, _P], _I),
     "hc_profile_enable": ([_I], _I),
     "hc_profile_collect": ([ctypes.POINTER(KernelStat), _I, ctypes.POINTER(_I)], _I),
 }
@@ -188,6 +190,15 @@ def hc_sum3_workspace_bytes(D: int, dtype: int, batch: int = 1) -> int:
 def hc_sum3_batch(x1: int, x2: int, x3: int, z: int, D: int, dtype: int, batch: int, ws: int, ws_bytes: int,
                   stream: int) -> int:
     return lib().hc_sum3_batch(x1, x2, x3, z, D, dtype, batch, ws, ws_bytes, stream)
+
+
+def hc_ternary_workspace_bytes(D: int, dtype: int, batch: int = 1) -> int:
+    return lib().hc_ternary_workspace_bytes(D, dtype, batch)
+
+
+def hc_ternary_convolve_batch(a: int, b: int, z: int, D: int, dtype: int, batch: int, ws: int, ws_bytes: int,
+                              stream: int) -> int:
+    return lib().hc_ternary_convolve_batch(a, b, z, D, dtype, batch, ws, ws_bytes, stream)
 
 
 HC_MAXCONV_ROUND = 1

@@ -229,6 +229,27 @@ def test_sum3_validation():
     assert f(x1, x2, x3, z, 8, 0, 1, z + 64, big, 0) == 4         # workspace overlaps z
 
 
+def test_ternary_validation():
+    a, b, z, ws = FAKE, FAKE + (1 << 22), FAKE + (1 << 26), FAKE + (1 << 34)
+    f = _abi.hc_ternary_convolve_batch
+    big = 1 << 30
+    # workspace: four forward staging copies of 6^p 3^K entries and two
+    # inverse ones of 6^p 5^K per item (K = 4 inner axes, p = D - K)
+    assert _abi.hc_ternary_workspace_bytes(4, _abi.HC_F64, 1) == 0
+    assert _abi.hc_ternary_workspace_bytes(6, _abi.HC_F64, 2) == 2 * (4 * 36 * 81 + 2 * 36 * 625) * 8
+    assert _abi.hc_ternary_workspace_bytes(5, _abi.HC_F32, 1) == (4 * 6 * 81 + 2 * 6 * 625) * 4
+    assert _abi.hc_ternary_workspace_bytes(13, _abi.HC_F64, 1) == _abi.SIZE_MAX
+    assert _abi.hc_ternary_workspace_bytes(8, 9, 1) == _abi.SIZE_MAX
+    assert f(0, b, z, 6, 0, 1, ws, big, 0) == 1                   # null input
+    assert f(a, b, z, 13, 0, 1, ws, big, 0) == 2                  # D above 12
+    assert f(a, b, z, 6, 7, 1, ws, big, 0) == 3                   # dtype
+    assert f(a, b, z, 6, 0, 0, ws, big, 0) == 1                   # batch 0
+    assert f(a + 4, b, z, 6, 0, 1, ws, big, 0) == 5               # misaligned
+    assert f(a, b, z, 6, 0, 1, 0, 0, 0) == 6                      # workspace missing
+    assert f(a, b, b + 8, 6, 0, 1, ws, big, 0) == 4               # z overlaps b
+    assert f(a, b, z, 6, 0, 1, z + 64, big, 0) == 4               # workspace overlaps z
+
+
 def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     """Without libhc.so the binding raises instead of computing anything
     another way (there is no CPU fallback)."""

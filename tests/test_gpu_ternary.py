@@ -1,0 +1,138 @@
+"""GPU parity of the convolution of two ternary cubes (hc_ternary_convolve_
+batch; the sum of four Bernoulli-axis vectors from two pair sums) through the
+C ABI: every dtype bitwise against the oracle's six-product per-axis method;
+integers bitwise against the definition; batches; the sum of four against the
+oracle's composition and the four-fold definition; D = 12 in full against
+exact integers."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import hc_inputs
+import oracle
+import paper_1608_00206_amd as hc
+from tests import pins
+
+pytestmark = pytest.mark.gpu
+
+DEV = torch.device("cuda:0")
+DTYPES = [np.float64, np.float32, np.int64]
+
+
+def say(msg):
+    print(f"[ternary] {msg}", file=sys.stderr, flush=True)
+
+
+def on_gpu(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def pair(D, dtype, seed, batch=None, lo=0, hi=16):
+    g = np.random.default_rng([hc_inputs.SEED, 95, seed, D])
+    shape = (3 ** D,) if batch is None else (batch, 3 ** D)
+    if np.dtype(dtype) == np.int64:
+        return [g.integers(lo, hi, shape, dtype=np.int64) for _ in range(2)]
+    out = []
+    for _ in range(2):
+        u = g.random(shape)
+        out.append((u / u.sum(axis=-1, keepdims=True)).astype(dtype))
+    return out
+
+
+def run(a, b):
+    return hc.ternary_convolve(on_gpu(a), on_gpu(b))
+
+
+# K = 4 inner axes in the fused tile; D > 4 adds outer axes in groups of 2
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("D", [0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10])
+def test_ternary_matches_oracle_method(dtype, D):
+    a, b = pair(D, dtype, 1)
+    say(f"D={D} {np.dtype(dtype).name}")
+    z = run(a, b)
+    torch.cuda.synchronize(DEV)
+    pins.assert_bitwise(z.cpu().numpy(), oracle.ternary_canonical(a, b), f"ternary D={D}")
+
+
+@pytest.mark.parametrize("D", [0, 3, 6])
+def test_ternary_int64_matches_definition(D):
+    a, b = pair(D, np.int64, 2, lo=-16, hi=16)
+    z = run(a, b)
+    torch.cuda.synchronize(DEV)
+    pins.assert_bitwise(z.cpu().numpy(), oracle.ternary_naive(a, b), f"ternary int64 definition D={D}")
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("D,B", [(3, 4), (7, 3)])
+def test_ternary_batch_and_inputs_unchanged(dtype, D, B):
+    a, b = pair(D, dtype, 3, batch=B)
+    ta, tb = on_gpu(a), on_gpu(b)
+    ca, cb = ta.clone(), tb.clone()
+    z = hc.ternary_convolve_batch(ta, tb)
+    torch.cuda.synchronize(DEV)
+    assert torch.equal(ta, ca) and torch.equal(tb, cb)
+    z = z.cpu().numpy()
+    for i in range(B):
+        pins.assert_bitwise(z[i], oracle.ternary_canonical(a[i], b[i]), f"item {i}")
+
+
+def test_sum4_matches_oracle_composition():
+    """hc.sum4 = the pair sums by convolve (bitwise the two-operand oracle),
+    then the ternary convolution (bitwise the oracle's six-product method)."""
+    D = 8
+    g = np.random.default_rng([hc_inputs.SEED, 96])
+    xs = []
+    for _ in range(4):
+        u = g.random(1 << D)
+        xs.append(u / u.sum())
+    z = hc.sum4(*(on_gpu(x) for x in xs))
+    torch.cuda.synchronize(DEV)
+    expect = oracle.ternary_canonical(oracle.canonical(xs[0], xs[1]), oracle.canonical(xs[2], xs[3]))
+    pins.assert_bitwise(z.cpu().numpy(), expect, "sum of four D=8")
+
+
+def test_sum4_int64_matches_fourfold_definition():
+    D = 3
+    g = np.random.default_rng([hc_inputs.SEED, 98])
+    xs = [g.integers(-8, 8, 1 << D, dtype=np.int64) for _ in range(4)]
+    z = hc.sum4(*(on_gpu(x) for x in xs)).cpu().numpy()
+
+    def quint(i):
+        f, w = 0, 1
+        for _ in range(D):
+            f += (i & 1) * w
+            i >>= 1
+            w *= 5
+        return f
+    expect = np.zeros(5 ** D, dtype=np.int64)
+    q = [quint(i) for i in range(1 << D)]
+    for i in range(1 << D):
+        for j in range(1 << D):
+            for k in range(1 << D):
+                for m in range(1 << D):
+                    expect[q[i] + q[j] + q[k] + q[m]] += xs[0][i] * xs[1][j] * xs[2][k] * xs[3][m]
+    pins.assert_bitwise(z, expect, "sum of four, int64, four-fold definition")
+
+
+def test_ternary_d12_full_size_exact():
+    """D = 12 (5^12 = 244M outputs): integer inputs in [0, 16) keep every
+    forward value below 3^12 * 15 and every product below 2^46, and the
+    method has no division, so it is exact in float64 too.  Every float64
+    output must equal the int64 one, and sampled int64 outputs the
+    definition."""
+    D = 12
+    a, b = pair(D, np.int64, 5)
+    say("D=12 int64 and float64: GPU")
+    zi = run(a, b)
+    zf = hc.ternary_convolve(on_gpu(a.astype(np.float64)), on_gpu(b.astype(np.float64)))
+    torch.cuda.synchronize(DEV)
+    assert torch.equal(zf, zi.to(torch.float64))
+    ks = np.unique(np.random.default_rng([hc_inputs.SEED, 99]).integers(0, 5 ** D, 512, dtype=np.uint64))
+    got = zi[torch.from_numpy(ks.astype(np.int64)).to(DEV)].cpu().numpy()
+    ref = oracle.ternary_direct_at(a.astype(np.float64), b.astype(np.float64), ks)
+    assert np.array_equal(got.astype(np.float64), ref)
+    assert int(zi.sum().item()) == int(a.sum()) * int(b.sum())
+    del zi, zf
+    torch.cuda.empty_cache()
