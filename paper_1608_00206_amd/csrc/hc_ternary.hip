@@ -20,9 +20,9 @@
 // 3^d, is the coordinate on axis D-1-d: the layout of the hypercube
 // convolution's output); z holds 5^D values, base-5 digit d = axis D-1-d.
 //
-// GPU schedule (K = min(D, 4) inner axes, p = D - K outer axes, in groups of
-// at most 2):
-//   outer forward   T on the outer axes, ascending, both operands:
+// GPU schedule (K = min(D, 4) inner axes, p = D - K outer axes):
+//   outer forward   T on the outer axes, ascending, both operands, in
+//                   groups of at most 2:
 //                   [6^a][3^M][L] -> [6^a][6^M][L]             (k_tn_fwd)
 //   fused inner     per outer index o: T on the K inner axes of the two
 //                   rows, the product, U on the inner axes, a contiguous
@@ -30,8 +30,9 @@
 //                   registers, seven tiles per workgroup       (k_tn_tile4)
 //                   (D < 4: one all-LDS tile of D axes          k_tn_fused)
 //   outer inverse   U on the outer axes, descending, out of place:
-//                   [6^a][6^M][L] -> [6^a][5^M][L], the last pass into z
-//                                                               (k_tn_inv)
+//                   [6^a][6^M][L] -> [6^a][5^M][L], the last pass into z;
+//                   groups of 3 with the outermost axis across waves
+//                   (k_tn_inv3w), then p mod 3 axes in registers (k_tn_inv)
 #include "hc.h"
 
 #include <hip/hip_runtime.h>
@@ -288,6 +289,59 @@ __device__ __forceinline__ void u_two(const T (&p)[36], T (&c)[25])
                c[2 * 5 + k1], c[3 * 5 + k1], c[4 * 5 + k1]);
 }
 
+// Outer inverse on three axes, out of place, with the group's outermost
+// axis across the workgroup's six waves: in [n_hi][6^3][L] -> out
+// [n_hi][5^3][L].  A workgroup takes 64 consecutive columns (lanes past L
+// take part in the barrier only); wave w holds digit w of the outermost axis
+// and its lanes' 36 registers the two inner axes (row 36 w + t).  U runs on
+// the two inner axes in registers (36 -> 25 values), then on the outermost
+// axis through LDS: every wave writes its 25 values, and wave w then takes
+// the register indices k = w, w + 6, ... below 25 with all six digits and
+// stores rows 25 c + k.
+constexpr int TN_INV3_NT = 384;
+
+template <typename T>
+__global__ __launch_bounds__(TN_INV3_NT) void k_tn_inv3w(const T* __restrict__ in, T* __restrict__ out,
+                                                         uint64_t in_bs, uint64_t out_bs, uint64_t L,
+                                                         uint32_t tiles_per_hi, uint32_t n_tiles)
+{
+    __shared__ T S[6 * 25 * 64];
+    const uint32_t tile = blockIdx.x;
+    if (tile >= n_tiles) return;  // the whole workgroup
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const uint32_t hi = tile / tiles_per_hi, j = tile - hi * tiles_per_hi;
+    const uint64_t col = (uint64_t)j * 64 + lane;
+    const bool act = col < L;
+    const T* src = in + (uint64_t)blockIdx.y * in_bs + (uint64_t)hi * 216 * L + col;
+    T* dst = out + (uint64_t)blockIdx.y * out_bs + (uint64_t)hi * 125 * L + col;
+    T v[36];
+#pragma unroll
+    for (int t = 0; t < 36; ++t) v[t] = act ? src[(uint64_t)(w * 36 + t) * L] : T(0);
+    T c[25];
+    u_two(v, c);
+#pragma unroll
+    for (int k = 0; k < 25; ++k) S[(w * 25 + k) * 64 + lane] = c[k];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+        const int k = w + 6 * q;
+        if (k < 25) {
+            T r0, r1, r2, r3, r4;
+            u_line(S[(0 * 25 + k) * 64 + lane], S[(1 * 25 + k) * 64 + lane], S[(2 * 25 + k) * 64 + lane],
+                   S[(3 * 25 + k) * 64 + lane], S[(4 * 25 + k) * 64 + lane], S[(5 * 25 + k) * 64 + lane], r0, r1,
+                   r2, r3, r4);
+            if (act) {
+                dst[(uint64_t)(0 * 25 + k) * L] = r0;
+                dst[(uint64_t)(1 * 25 + k) * L] = r1;
+                dst[(uint64_t)(2 * 25 + k) * L] = r2;
+                dst[(uint64_t)(3 * 25 + k) * L] = r3;
+                dst[(uint64_t)(4 * 25 + k) * L] = r4;
+            }
+        }
+    }
+}
+
 // The fused tile for K = 4, every step on two axes held in one thread's
 // registers; a workgroup takes TN_TPB tiles at once (36 threads each).
 // Tile digits: axes 0..3 with ternary digits b0..b3 (inputs) and six-slot
@@ -383,7 +437,8 @@ struct TnPlan {
     uint64_t n3 = 0, n5 = 0;
     uint64_t fwd_stage = 0;  // 6^p 3^K: elements of a forward staging buffer per operand and item
     uint64_t inv_stage = 0;  // 6^p 5^K: elements of an inverse staging buffer per item
-    std::vector<int> groups;  // outer axes per group, ascending from axis 0
+    std::vector<int> groups;      // forward: outer axes per group (at most 2), ascending from axis 0
+    std::vector<int> inv_groups;  // inverse: p mod 3 axes first, then groups of 3
 };
 
 TnPlan make_tn_plan(int D)
@@ -399,6 +454,8 @@ TnPlan make_tn_plan(int D)
         P.groups.push_back(m);
         left -= m;
     }
+    if (P.p % 3) P.inv_groups.push_back(P.p % 3);
+    for (int i = 0; i < P.p / 3; ++i) P.inv_groups.push_back(3);
     P.fwd_stage = P.p > 0 ? powc(6, P.p) * powc(3, P.K) : 0;
     P.inv_stage = P.p > 0 ? powc(6, P.p) * powc(5, P.K) : 0;
     return P;
@@ -428,6 +485,17 @@ void launch_tn_inv(const T* in, T* out, uint64_t in_bs, uint64_t out_bs, uint64_
     LaunchScope scope(s, (double)batch * n_cols * (powc(6, M) + powc(5, M)) * sizeof(T), "tn_inv<%s,M=%d>",
                       tname<T>(), M);
     k_tn_inv<T, M><<<grid, TN_NT, 0, s>>>(in, out, in_bs, out_bs, n_cols, L);
+}
+
+template <typename T>
+void launch_tn_inv3(const T* in, T* out, uint64_t in_bs, uint64_t out_bs, uint64_t n_hi, uint64_t L, int batch,
+                    hipStream_t s)
+{
+    const uint32_t tiles_per_hi = (uint32_t)((L + 63) / 64);
+    const uint32_t n_tiles = (uint32_t)(n_hi * tiles_per_hi);
+    dim3 grid(n_tiles, batch, 1);
+    LaunchScope scope(s, (double)batch * n_hi * L * (216.0 + 125.0) * sizeof(T), "tn_inv<%s,M=3>", tname<T>());
+    k_tn_inv3w<T><<<grid, TN_INV3_NT, 0, s>>>(in, out, in_bs, out_bs, L, tiles_per_hi, n_tiles);
 }
 
 template <typename T, int K>
@@ -487,8 +555,8 @@ int run_tn(const TnPlan& P, const T* a, const T* b, T* z, int batch, T* ws, int 
     // outer inverse, descending, out of place; the last pass writes z
     int top = P.p;
     int buf = 0;
-    for (int gi = (int)P.groups.size() - 1; gi >= 0; --gi) {
-        const int M = P.groups[gi];
+    for (int gi = (int)P.inv_groups.size() - 1; gi >= 0; --gi) {
+        const int M = P.inv_groups[gi];
         const int a0 = top - M;
         const uint64_t L = powc(5, D - top);
         const uint64_t n_cols = powc(6, a0) * L;
@@ -496,7 +564,8 @@ int run_tn(const TnPlan& P, const T* a, const T* b, T* z, int batch, T* ws, int 
         T* out = last ? z : iv[buf ^ 1];
         const uint64_t out_bs = last ? P.n5 : P.inv_stage;
         if (M == 1) launch_tn_inv<T, 1>(iv[buf], out, P.inv_stage, out_bs, n_cols, L, batch, s);
-        else launch_tn_inv<T, 2>(iv[buf], out, P.inv_stage, out_bs, n_cols, L, batch, s);
+        else if (M == 2) launch_tn_inv<T, 2>(iv[buf], out, P.inv_stage, out_bs, n_cols, L, batch, s);
+        else launch_tn_inv3<T>(iv[buf], out, P.inv_stage, out_bs, powc(6, a0), L, batch, s);
         buf ^= 1;
         top = a0;
     }
