@@ -343,11 +343,20 @@ def ternary_convolve(a: torch.Tensor, b: torch.Tensor, out: torch.Tensor | None 
     return ternary_convolve_batch(a.view(1, n), b.view(1, n), out=flat, workspace=workspace).view(-1)
 
 
+def sum4_batch(x1: torch.Tensor, x2: torch.Tensor, x3: torch.Tensor, x4: torch.Tensor) -> torch.Tensor:
+    """Distribution of X1 + X2 + X3 + X4 for (B, 2^D) distributions over
+    {0,1}^D: the pair sums by convolve_batch, then their ternary
+    convolution.  Returns (B, 5^D), base-5 digit = the sum of the four
+    coordinates."""
+    return ternary_convolve_batch(convolve_batch(x1, x2), convolve_batch(x3, x4))
+
+
 def sum4(x1: torch.Tensor, x2: torch.Tensor, x3: torch.Tensor, x4: torch.Tensor) -> torch.Tensor:
-    """Distribution of X1 + X2 + X3 + X4 for four (2^D,) distributions over
-    {0,1}^D: the pair sums by convolve, then their ternary convolution.
-    Returns (5^D,), base-5 digit = the sum of the four coordinates."""
-    return ternary_convolve(convolve(x1, x2), convolve(x3, x4))
+    """Single form of sum4_batch: (2^D,) inputs, (5^D,) output."""
+    if x1.dim() != 1:
+        raise ValueError("x1 ... x4 must be 1-D tensors of length 2^D")
+    n = x1.numel()
+    return sum4_batch(*(x.view(1, n) for x in (x1, x2, x3, x4))).view(-1)
 
 
 def difference(x: torch.Tensor, y: torch.Tensor, out: torch.Tensor | None = None,

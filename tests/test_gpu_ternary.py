@@ -93,6 +93,22 @@ def test_sum4_matches_oracle_composition():
     pins.assert_bitwise(z.cpu().numpy(), expect, "sum of four D=8")
 
 
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_sum4_batch_matches_single_calls(dtype):
+    D, B = 6, 3
+    g = np.random.default_rng([hc_inputs.SEED, 97])
+    if np.dtype(dtype) == np.int64:
+        xs = [g.integers(0, 8, (B, 1 << D), dtype=np.int64) for _ in range(4)]
+    else:
+        xs = [g.random((B, 1 << D)).astype(dtype) for _ in range(4)]
+    zb = hc.sum4_batch(*(on_gpu(x) for x in xs)).cpu().numpy()
+    for i in range(B):
+        zi = hc.sum4(*(on_gpu(x[i]) for x in xs)).cpu().numpy()
+        pins.assert_bitwise(zb[i], zi, f"item {i}")
+        expect = oracle.ternary_canonical(oracle.canonical(xs[0][i], xs[1][i]), oracle.canonical(xs[2][i], xs[3][i]))
+        pins.assert_bitwise(zb[i], expect, f"item {i} vs oracle")
+
+
 def test_sum4_int64_matches_fourfold_definition():
     D = 3
     g = np.random.default_rng([hc_inputs.SEED, 98])
