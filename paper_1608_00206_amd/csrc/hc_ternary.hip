@@ -295,9 +295,9 @@ __device__ __forceinline__ void u_two(const T (&p)[36], T (&c)[25])
 // take part in the barrier only); wave w holds digit w of the outermost axis
 // and its lanes' 36 registers the two inner axes (row 36 w + t).  U runs on
 // the two inner axes in registers (36 -> 25 values), then on the outermost
-// axis through LDS: every wave writes its 25 values, and wave w then takes
-// the register indices k = w, w + 6, ... below 25 with all six digits and
-// stores rows 25 c + k.
+// axis through LDS in five sub-rounds of five register indices: every wave
+// writes its five values, and wave w < 5 then takes index k = 5 r + w with
+// all six digits and stores rows 25 c + k.
 constexpr int TN_INV3_NT = 384;
 
 template <typename T>
@@ -305,7 +305,7 @@ __global__ __launch_bounds__(TN_INV3_NT) void k_tn_inv3w(const T* __restrict__ i
                                                          uint64_t in_bs, uint64_t out_bs, uint64_t L,
                                                          uint32_t tiles_per_hi, uint32_t n_tiles)
 {
-    __shared__ T S[6 * 25 * 64];
+    __shared__ T S[6 * 5 * 64];
     const uint32_t tile = blockIdx.x;
     if (tile >= n_tiles) return;  // the whole workgroup
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -320,17 +320,20 @@ __global__ __launch_bounds__(TN_INV3_NT) void k_tn_inv3w(const T* __restrict__ i
     for (int t = 0; t < 36; ++t) v[t] = act ? src[(uint64_t)(w * 36 + t) * L] : T(0);
     T c[25];
     u_two(v, c);
+    // five sub-rounds of five register indices: every wave writes its five
+    // values, then wave w < 5 takes index 5 r + w with all six digits
 #pragma unroll
-    for (int k = 0; k < 25; ++k) S[(w * 25 + k) * 64 + lane] = c[k];
-    __syncthreads();
+    for (int r = 0; r < 5; ++r) {
+        if (r > 0) __syncthreads();  // the previous sub-round's reads are done
 #pragma unroll
-    for (int q = 0; q < 5; ++q) {
-        const int k = w + 6 * q;
-        if (k < 25) {
+        for (int i = 0; i < 5; ++i) S[(w * 5 + i) * 64 + lane] = c[5 * r + i];
+        __syncthreads();
+        if (w < 5) {
+            const int k = 5 * r + w;
             T r0, r1, r2, r3, r4;
-            u_line(S[(0 * 25 + k) * 64 + lane], S[(1 * 25 + k) * 64 + lane], S[(2 * 25 + k) * 64 + lane],
-                   S[(3 * 25 + k) * 64 + lane], S[(4 * 25 + k) * 64 + lane], S[(5 * 25 + k) * 64 + lane], r0, r1,
-                   r2, r3, r4);
+            u_line(S[(0 * 5 + w) * 64 + lane], S[(1 * 5 + w) * 64 + lane], S[(2 * 5 + w) * 64 + lane],
+                   S[(3 * 5 + w) * 64 + lane], S[(4 * 5 + w) * 64 + lane], S[(5 * 5 + w) * 64 + lane], r0, r1, r2,
+                   r3, r4);
             if (act) {
                 dst[(uint64_t)(0 * 25 + k) * L] = r0;
                 dst[(uint64_t)(1 * 25 + k) * L] = r1;
