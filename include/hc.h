@@ -254,12 +254,25 @@ int hc_convolve_backward(const void* x, const void* y, const void* grad_z,
  * The groups are independent branches of one HIP graph, captured on the
  * first execution (and again whenever the buffers change) and replayed.
  * Results are bitwise those of hc_convolve on each pair.
+ *
+ * With HC_PLAN_PERSISTENT_PAIRS the graph holds one kernel launch instead: a
+ * persistent grid (as many workgroups as stay resident, at most one per
+ * pair) whose workgroups take pairs by ticket from a list sorted by
+ * decreasing D and each run the whole single-pair path of their pair (outer
+ * forward, fused tiles, outer inverse), separated by workgroup barriers.  No
+ * workgroup waits for another.  The schedule per D is fixed (largest fused
+ * tile, outer forward groups of at most three axes, outer inverse groups of
+ * six axes as 4 + 2, then 3 + 2, 2 + 2 or up to three register axes); the
+ * workspace holds one slot per workgroup.  Results are again bitwise those of
+ * hc_convolve.  Launches of one plan must not overlap in time (they share
+ * the plan's ticket counters as well as its workspace).
  */
 typedef struct hc_plan hc_plan;
 
 /* Plan flags */
 #define HC_PLAN_TUNE 1u        /* time candidate schedules per D at creation, keep the fastest */
-#define HC_PLAN_PERSISTENT 2u  /* one persistent kernel for all pairs: disabled, returns HC_ERR_UNSUPPORTED */
+#define HC_PLAN_PERSISTENT 2u  /* split pairs gated by phase counters: disabled, returns HC_ERR_UNSUPPORTED */
+#define HC_PLAN_PERSISTENT_PAIRS 4u  /* one persistent kernel launch, a workgroup per pair (above) */
 
 /*
  * Create a plan for n_pairs pairs with dimensions Ds[0..n_pairs) (host
@@ -268,8 +281,9 @@ typedef struct hc_plan hc_plan;
  * temporary buffers and times candidate schedules (this synchronises the
  * device); with the environment variable HC_TUNE_CACHE naming a file, tuned
  * choices are read from and appended to that file.
- * Errors: HC_ERR_INVALID_ARG (null Ds/out, n_pairs < 1, unknown flag),
- * HC_ERR_D_RANGE, HC_ERR_UNSUPPORTED, HC_ERR_NO_DEVICE, HC_ERR_HIP.
+ * Errors: HC_ERR_INVALID_ARG (null Ds/out, n_pairs < 1, unknown flag,
+ * HC_PLAN_PERSISTENT with HC_PLAN_PERSISTENT_PAIRS), HC_ERR_D_RANGE,
+ * HC_ERR_UNSUPPORTED, HC_ERR_NO_DEVICE, HC_ERR_HIP.
  */
 int hc_plan_create_batched(const int* Ds, int n_pairs, int dtype, unsigned flags, hc_plan** out);
 

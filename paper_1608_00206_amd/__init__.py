@@ -448,17 +448,21 @@ class BatchedPlan:
     occupy x_offsets[i]:x_offsets[i+1] of x_packed / y_packed, its z occupies
     z_offsets[i]:z_offsets[i+1] of the output.
     tune=True times candidate schedules per D at creation and keeps the
-    fastest; persistent=True asks for the single persistent kernel, which is
-    disabled (HCError HC_ERR_UNSUPPORTED).
+    fastest; persistent_pairs=True runs every pair in one persistent kernel
+    launch instead (a workgroup per pair, pairs taken by ticket in decreasing
+    D); persistent=True asks for the dependency-gated persistent kernel over
+    split pairs, which is disabled (HCError HC_ERR_UNSUPPORTED).
     """
 
-    def __init__(self, Ds, dtype: torch.dtype = torch.float64, tune: bool = False, persistent: bool = False):
+    def __init__(self, Ds, dtype: torch.dtype = torch.float64, tune: bool = False, persistent: bool = False,
+                 persistent_pairs: bool = False):
         import json
         self._h = None
         self._ws = None  # the plan's own workspace when the caller passes none
         self.Ds = [int(d) for d in Ds]
         self.dtype = dtype
-        flags = (_abi.HC_PLAN_TUNE if tune else 0) | (_abi.HC_PLAN_PERSISTENT if persistent else 0)
+        flags = ((_abi.HC_PLAN_TUNE if tune else 0) | (_abi.HC_PLAN_PERSISTENT if persistent else 0)
+                 | (_abi.HC_PLAN_PERSISTENT_PAIRS if persistent_pairs else 0))
         self._h = _abi.hc_plan_create_batched(self.Ds, DTYPES[dtype], flags)
         self.x_offsets, self.z_offsets = _abi.hc_plan_layout(self._h, len(self.Ds))
         self.workspace_bytes = _abi.hc_plan_workspace_bytes(self._h)

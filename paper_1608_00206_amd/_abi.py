@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(HERE, "libhc.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "hc.h")
 
 HC_F64, HC_F32, HC_I64 = 0, 1, 2
-HC_PLAN_TUNE, HC_PLAN_PERSISTENT = 1, 2
+HC_PLAN_TUNE, HC_PLAN_PERSISTENT, HC_PLAN_PERSISTENT_PAIRS = 1, 2, 4
 HC_OK = 0
 STATUS_NAMES = {
     0: "HC_OK", 1: "HC_ERR_INVALID_ARG", 2: "HC_ERR_D_RANGE", 3: "HC_ERR_UNSUPPORTED",

@@ -17,7 +17,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhc.so")
 SOURCES = [os.path.join(CSRC, f) for f in ("hc_api.hip", "hc_batched.hip", "hc_apps.hip", "hc_noalloc.hip", "hc_sum3.hip",
-                                            "hc_ternary.hip")]
+                                            "hc_ternary.hip", "hc_persistent.hip")]
 HEADERS = [os.path.join(CSRC, f) for f in ("hc_device.hpp", "hc_kernels.hpp", "hc_internal.hpp")] + \
           [os.path.join(ROOT, "include", "hc.h")]
 

@@ -65,6 +65,15 @@ struct hc_plan {
     const void* g_y = nullptr;
     void* g_z = nullptr;
     void* g_ws = nullptr;
+    // HC_PLAN_PERSISTENT_PAIRS: one persistent kernel, a workgroup per pair
+    bool pairs = false;
+    uint32_t grid = 0;                  // workgroups of the persistent launch
+    int per_cu = 0;                     // resident workgroups per CU
+    uint64_t slot_elems = 0;            // workspace elements per workgroup
+    std::vector<hc::PairPlan> plans;    // by D
+    hc::PairTask* d_tasks = nullptr;    // ticket order: decreasing D
+    hc::PairPlan* d_plans = nullptr;
+    uint32_t* d_counters = nullptr;     // ticket counter, workgroups finished
 };
 
 namespace hc {
@@ -151,6 +160,44 @@ static int finalize(hc_plan* pl)
     return HC_OK;
 }
 
+// Persistent mode: per-D schedules, the ticket-ordered task list (pairs by
+// decreasing D, ties in pair order), the workspace slots and the counters.
+static int finalize_pairs(hc_plan* pl)
+{
+    constexpr int ND = 17;  // batched pairs have D <= 16
+    pl->plans.assign(ND, PairPlan());
+    for (int D = 0; D < ND; ++D) pl->plans[D] = pair_plan(D, pl->dtype);
+    std::vector<int> order(pl->n_pairs);
+    for (int i = 0; i < pl->n_pairs; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return pl->Ds[a] > pl->Ds[b]; });
+    std::vector<PairTask> tasks(pl->n_pairs);
+    pl->slot_elems = 0;
+    pl->alg_bytes = 0;
+    for (int t = 0; t < pl->n_pairs; ++t) {
+        const int q = order[t];
+        const int D = pl->Ds[q];
+        tasks[t].x_off = pl->x_off[q];
+        tasks[t].z_off = pl->z_off[q];
+        tasks[t].D = (uint32_t)D;
+        pl->slot_elems = std::max<uint64_t>(pl->slot_elems, pair_slot_elems(pl->plans[D]));
+        pl->alg_bytes += pair_alg_bytes(pl->plans[D], D, pl->es);
+    }
+    int rc = pairs_per_cu(pl->dtype, &pl->per_cu);
+    if (rc != HC_OK) return rc;
+    const uint64_t g = std::min<uint64_t>((uint64_t)pl->n_pairs, (uint64_t)pl->cus * pl->per_cu);
+    pl->grid = (uint32_t)(g ? g : 1);
+    pl->ws_bytes = pl->slot_elems ? ((pl->grid * pl->slot_elems * pl->es + 255) & ~255ull) : 0;
+    hipError_t e = hipMalloc(&pl->d_tasks, tasks.size() * sizeof(PairTask));
+    if (e == hipSuccess) e = hipMalloc(&pl->d_plans, ND * sizeof(PairPlan));
+    if (e == hipSuccess) e = hipMalloc(&pl->d_counters, 2 * sizeof(uint32_t));
+    if (e == hipSuccess)
+        e = hipMemcpy(pl->d_tasks, tasks.data(), tasks.size() * sizeof(PairTask), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(pl->d_plans, pl->plans.data(), ND * sizeof(PairPlan), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(pl->d_counters, 0, 2 * sizeof(uint32_t));
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    return e == hipSuccess ? HC_OK : hip_fail(e, "persistent plan tables");
+}
+
 template <typename T>
 static int enqueue_groups(hc_plan* pl, const void* x, const void* y, void* z, void* ws)
 {
@@ -187,11 +234,15 @@ static int capture(hc_plan* pl, const void* x, const void* y, void* z, void* ws)
     int rc;
     {
         CaptureScope quiet;  // the profiler records nothing while capturing
-        switch (pl->dtype) {
-            case HC_F64: rc = enqueue_groups<double>(pl, x, y, z, ws); break;
-            case HC_F32: rc = enqueue_groups<float>(pl, x, y, z, ws); break;
-            default: rc = enqueue_groups<uint64_t>(pl, x, y, z, ws); break;
-        }
+        if (pl->pairs)
+            rc = launch_pairs_persistent(pl->dtype, x, y, z, ws, pl->slot_elems, pl->d_tasks, pl->d_plans,
+                                         (uint32_t)pl->n_pairs, pl->d_counters, pl->grid, pl->cap_stream);
+        else
+            switch (pl->dtype) {
+                case HC_F64: rc = enqueue_groups<double>(pl, x, y, z, ws); break;
+                case HC_F32: rc = enqueue_groups<float>(pl, x, y, z, ws); break;
+                default: rc = enqueue_groups<uint64_t>(pl, x, y, z, ws); break;
+            }
     }
     hipGraph_t graph = nullptr;
     e = hipStreamEndCapture(pl->cap_stream, &graph);
@@ -405,6 +456,9 @@ static void destroy(hc_plan* pl)
 {
     (void)release_exec(pl);
     for (Group& g : pl->groups) free_group_device(g);
+    if (pl->d_tasks) (void)hipFree(pl->d_tasks);
+    if (pl->d_plans) (void)hipFree(pl->d_plans);
+    if (pl->d_counters) (void)hipFree(pl->d_counters);
     if (pl->fork) (void)hipEventDestroy(pl->fork);
     if (pl->launched) (void)hipEventDestroy(pl->launched);
     if (pl->cap_stream) (void)hipStreamDestroy(pl->cap_stream);
@@ -414,7 +468,10 @@ static void destroy(hc_plan* pl)
 static int check_pairs(const int* Ds, int n_pairs, int dtype, unsigned flags)
 {
     if (!Ds || n_pairs < 1) return fail(HC_ERR_INVALID_ARG, "Ds required, n_pairs >= 1");
-    if ((flags & ~(HC_PLAN_TUNE | HC_PLAN_PERSISTENT)) != 0) return fail(HC_ERR_INVALID_ARG, "unknown plan flag");
+    if ((flags & ~(HC_PLAN_TUNE | HC_PLAN_PERSISTENT | HC_PLAN_PERSISTENT_PAIRS)) != 0)
+        return fail(HC_ERR_INVALID_ARG, "unknown plan flag");
+    if ((flags & HC_PLAN_PERSISTENT) && (flags & HC_PLAN_PERSISTENT_PAIRS))
+        return fail(HC_ERR_INVALID_ARG, "HC_PLAN_PERSISTENT and HC_PLAN_PERSISTENT_PAIRS exclude each other");
     if (dtype_size(dtype) == 0) return fail(HC_ERR_UNSUPPORTED, "unknown dtype %d", dtype);
     for (int i = 0; i < n_pairs; ++i)
         if (Ds[i] < 0 || Ds[i] > 16) return fail(HC_ERR_D_RANGE, "pair %d has D=%d outside [0, 16]", i, Ds[i]);
@@ -453,18 +510,21 @@ int hc_plan_create_batched(const int* Ds, int n_pairs, int dtype, unsigned flags
     pl->es = dtype_size(dtype);
     pl->flags = flags;
     pl->cus = cus;
+    pl->pairs = (flags & HC_PLAN_PERSISTENT_PAIRS) != 0;
     layout(pl, Ds, n_pairs);
     make_groups(pl);
     hipError_t e = hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&pl->fork, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&pl->launched, hipEventDisableTiming);
     rc = e == hipSuccess ? HC_OK : hip_fail(e, "plan stream");
-    if (rc == HC_OK) {
+    if (rc == HC_OK && pl->pairs) {
+        rc = finalize_pairs(pl);
+    } else if (rc == HC_OK) {
         if (flags & HC_PLAN_TUNE) rc = tune(pl);
         else
             for (Group& g : pl->groups) g.opts = default_opts();
+        if (rc == HC_OK) rc = finalize(pl);
     }
-    if (rc == HC_OK) rc = finalize(pl);
     if (rc != HC_OK) {
         destroy(pl);
         return rc;
@@ -510,7 +570,7 @@ int hc_plan_execute(hc_plan* plan, const void* x, const void* y, void* z, void* 
         if (rc != HC_OK) return rc;
     }
     const char* tn = plan->dtype == HC_F64 ? "f64" : (plan->dtype == HC_F32 ? "f32" : "i64");
-    LaunchScope scope(stream, plan->alg_bytes, "batched_graph<%s>", tn);
+    LaunchScope scope(stream, plan->alg_bytes, plan->pairs ? "pairs_persistent<%s>" : "batched_graph<%s>", tn);
     hipError_t e = hipGraphLaunch(plan->exec, stream);
     if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
     e = hipEventRecord(plan->launched, stream);
@@ -530,6 +590,28 @@ int hc_plan_check(hc_plan* plan)
 int hc_plan_describe(const hc_plan* plan, char* buf, size_t len)
 {
     if (!plan || !buf || len == 0) return fail(HC_ERR_INVALID_ARG, "plan and buffer required");
+    if (plan->pairs) {
+        std::string s = "{\"mode\": \"persistent_pairs\", \"tuned\": " +
+                        std::string((plan->flags & HC_PLAN_TUNE) ? "true" : "false") +
+                        ", \"grid\": " + std::to_string(plan->grid) + ", \"workgroups_per_cu\": " +
+                        std::to_string(plan->per_cu) + ", \"threads\": " + std::to_string(PAIR_NT) +
+                        ", \"groups\": [";
+        for (size_t i = 0; i < plan->groups.size(); ++i) {
+            const Group& g = plan->groups[i];
+            const PairPlan& pp = plan->plans[g.D];
+            std::string fwd, inv;
+            for (int k = 0; k < pp.n_fwd; ++k) fwd += (k ? ", " : "") + std::to_string(pp.fwd[k]);
+            for (int k = 0; k < pp.n_inv; ++k)
+                inv += (k ? ", " : "") + std::string("\"") + std::to_string(pp.inv_r[k]) + "+" +
+                       std::to_string(pp.inv_w[k]) + "\"";
+            s += (i ? ", " : "") + std::string("{\"D\": ") + std::to_string(g.D) +
+                 ", \"items\": " + std::to_string(g.items.size()) + ", \"K\": " + std::to_string(pp.K) +
+                 ", \"forward_groups\": [" + fwd + "], \"inverse_groups\": [" + inv + "]}";
+        }
+        s += "]}";
+        snprintf(buf, len, "%s", s.c_str());
+        return HC_OK;
+    }
     std::string s = "{\"mode\": \"graph\", \"tuned\": " + std::string((plan->flags & HC_PLAN_TUNE) ? "true" : "false") +
                     ", \"groups\": [";
     for (size_t i = 0; i < plan->groups.size(); ++i) {
@@ -562,14 +644,21 @@ int hc_plan_inspect(const int* Ds, int n_pairs, int dtype, unsigned flags, int64
     *n_groups = (int64_t)pl.groups.size();
     for (size_t i = 0; i < pl.groups.size() && (int64_t)i < capacity; ++i) {
         const Group& g = pl.groups[i];
-        const Plan P = make_plan(g.D, dtype, default_opts());
         int64_t* r = info + 6 * i;
         r[0] = g.D;
         r[1] = (int64_t)g.items.size();
         r[2] = g.items.front();
-        r[3] = P.K;
-        r[4] = (int64_t)P.k1.size();
-        r[5] = (int64_t)P.inv.size();
+        if (flags & HC_PLAN_PERSISTENT_PAIRS) {
+            const PairPlan pp = pair_plan(g.D, dtype);
+            r[3] = pp.K;
+            r[4] = pp.n_fwd;
+            r[5] = pp.n_inv;
+        } else {
+            const Plan P = make_plan(g.D, dtype, default_opts());
+            r[3] = P.K;
+            r[4] = (int64_t)P.k1.size();
+            r[5] = (int64_t)P.inv.size();
+        }
     }
     return HC_OK;
 }

@@ -120,4 +120,35 @@ template <typename T>
 int run_backward(const Plan& P, const T* x, const T* y, const T* gz, uint64_t gz_bs, T* gx, T* gy, int batch,
                  T* ws, int cus, hipStream_t s);
 
+// ---------------------------------------------- persistent batched kernel
+// Threads per workgroup: nine waves, one per digit pair of the two wave
+// axes of its LDS passes.
+constexpr int PAIR_NT = 576;
+
+// Schedule of one pair of dimension D in the persistent kernel: fused depth
+// K (K = D when D fits one tile, else the largest tile), p = D - K outer axes,
+// the outer forward groups (ascending) and the outer inverse passes in
+// execution order (axes [inv_a, inv_a + inv_r + inv_w), inv_r in registers).
+struct PairPlan {
+    uint8_t K = 0, p = 0, n_fwd = 0, n_inv = 0;
+    uint8_t fwd[4] = {0, 0, 0, 0};
+    uint8_t inv_a[4] = {0, 0, 0, 0}, inv_r[4] = {0, 0, 0, 0}, inv_w[4] = {0, 0, 0, 0};
+    uint32_t xt_elems = 0, tmp_elems = 0;  // per operand: x~ and the forward staging
+};
+
+// One entry of the ticket-ordered task list: a pair's dimension and element
+// offsets into the packed x / y and z.
+struct PairTask {
+    uint64_t x_off = 0, z_off = 0;
+    uint32_t D = 0, pad = 0;
+};
+
+PairPlan pair_plan(int D, int dtype);
+uint64_t pair_slot_elems(const PairPlan& pp);  // workspace elements per workgroup
+double pair_alg_bytes(const PairPlan& pp, int D, size_t es);
+int pairs_per_cu(int dtype, int* per_cu);      // resident workgroups per CU
+int launch_pairs_persistent(int dtype, const void* x, const void* y, void* z, void* ws, uint64_t slot_elems,
+                            const PairTask* tasks, const PairPlan* plans, uint32_t n_pairs, uint32_t* counters,
+                            uint32_t grid, hipStream_t s);
+
 }  // namespace hc

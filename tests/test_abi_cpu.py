@@ -140,6 +140,7 @@ def test_plan_validation():
     assert f(Ds, 3, 0, 0, None) == 1
     assert f(Ds, 3, 0, 8, ctypes.byref(out)) == 1          # unknown flag
     assert f(Ds, 3, 0, 2, ctypes.byref(out)) == 3          # persistent kernel disabled
+    assert f(Ds, 3, 0, 2 | 4, ctypes.byref(out)) == 1      # the two persistent modes exclude each other
     assert f(Ds, 3, 7, 0, ctypes.byref(out)) == 3          # unknown dtype
     bad = (ctypes.c_int * 2)(4, 17)
     assert f(bad, 2, 0, 0, ctypes.byref(out)) == 2

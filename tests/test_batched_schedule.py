@@ -43,3 +43,19 @@ def test_inspect_and_plan_validation():
     with pytest.raises(_abi.HCError) as e:
         _abi.hc_plan_inspect([9, 12], _abi.HC_F64, _abi.HC_PLAN_PERSISTENT)
     assert e.value.status == "HC_ERR_UNSUPPORTED"
+
+
+@pytest.mark.parametrize("dtype", [_abi.HC_F64, _abi.HC_F32, _abi.HC_I64])
+def test_persistent_pair_schedules(dtype):
+    """One persistent launch, a workgroup per pair: the largest fused tile
+    (9 axes for 4-byte elements, else 8), outer forward groups of at most
+    three axes, outer inverse groups of at most six."""
+    groups = _abi.hc_plan_inspect(list(range(0, 17)), dtype, _abi.HC_PLAN_PERSISTENT_PAIRS)
+    kmax = 9 if dtype == _abi.HC_F32 else 8
+    assert [g["D"] for g in groups] == list(range(16, -1, -1))
+    for g in groups:
+        D = g["D"]
+        assert g["K"] == min(D, kmax)
+        p = D - g["K"]
+        assert g["fwd_passes"] == -(-p // 3)
+        assert g["inv_passes"] == -(-p // 6)

@@ -125,3 +125,78 @@ def test_persistent_request_is_rejected():
     with pytest.raises(hc.HCError) as e:
         hc.BatchedPlan([9, 12], torch.float64, persistent=True)
     assert e.value.status == "HC_ERR_UNSUPPORTED"
+
+
+# ------------------------------------------- one persistent launch (HC_PLAN_PERSISTENT_PAIRS)
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32, np.int64])
+def test_persistent_pairs_match_oracle(dtype):
+    """Every schedule shape of the persistent kernel: single tiles (D up to
+    the largest fused depth), one to six outer axes (one inverse pass of 1+0,
+    2+0, 3+0, 2+2, 3+2 or 4+2), against the oracle pair by pair."""
+    Ds = [0, 1, 5, 8, 9, 12, 3, 10, 13, 6, 11, 2, 14, 7, 9, 4]
+    print(f"persistent pairs {np.dtype(dtype).name} Ds={Ds}", flush=True)
+    plan = hc.BatchedPlan(Ds, NP2T[np.dtype(dtype)], persistent_pairs=True)
+    assert plan.schedule["mode"] == "persistent_pairs"
+    assert 1 <= plan.schedule["grid"] <= len(Ds)
+    xs, ys = packed_inputs(Ds, dtype, seed=11)
+    check_pairs(plan, Ds, xs, ys, run_plan(plan, xs, ys))
+    plan.close()
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_persistent_pairs_largest_d_equal_single_calls(dtype):
+    """D = 15 and 16: three outer forward groups and two inverse passes;
+    bitwise equal to single-pair calls."""
+    Ds = [16, 3, 15, 9]
+    print(f"persistent pairs {np.dtype(dtype).name} Ds={Ds}", flush=True)
+    plan = hc.BatchedPlan(Ds, NP2T[np.dtype(dtype)], persistent_pairs=True)
+    xs, ys = packed_inputs(Ds, dtype, seed=12)
+    Z = run_plan(plan, xs, ys)
+    for i, D in enumerate(Ds):
+        z1 = hc.convolve(torch.from_numpy(xs[i]).to(DEV), torch.from_numpy(ys[i]).to(DEV)).cpu().numpy()
+        pins.assert_bitwise(Z[plan.z_offsets[i]:plan.z_offsets[i + 1]], z1, f"pair {i} D={D}")
+    plan.close()
+
+
+def test_persistent_pairs_many_tickets_per_workgroup():
+    """Far more pairs than workgroups: every workgroup takes many tickets.
+    Replays of the captured launch (the counters reset themselves) and a new
+    set of buffers all give the graph mode's bits."""
+    rng = np.random.default_rng(5)
+    Ds = [int(d) for d in rng.integers(0, 11, 1500)]
+    print(f"persistent pairs f64 {len(Ds)} pairs", flush=True)
+    plan = hc.BatchedPlan(Ds, torch.float64, persistent_pairs=True)
+    assert plan.schedule["grid"] < len(Ds)
+    ref = hc.BatchedPlan(Ds, torch.float64)
+    xs, ys = packed_inputs(Ds, np.float64, seed=13)
+    X = torch.from_numpy(np.concatenate(xs)).to(DEV)
+    Y = torch.from_numpy(np.concatenate(ys)).to(DEV)
+    Zr = ref.run(X, Y).cpu().numpy()
+    Z1 = plan.run(X, Y)
+    for _ in range(3):
+        plan.run(X, Y, out=Z1)
+    Z2 = plan.run(X.clone(), Y.clone())
+    plan.check()
+    pins.assert_bitwise(Z1.cpu().numpy(), Zr, "replayed")
+    pins.assert_bitwise(Z2.cpu().numpy(), Zr, "new buffers")
+    zo = plan.z_offsets
+    for i in (0, 1, 777, len(Ds) - 1):
+        pins.assert_bitwise(Zr[zo[i]:zo[i + 1]], oracle.canonical(xs[i], ys[i]), f"pair {i}")
+    plan.close()
+    ref.close()
+
+
+def test_persistent_pairs_config_mix():
+    """A slice of the batched workload (D drawn from {6, ..., 14}), bitwise
+    equal to the graph mode and, pair by pair, to the oracle."""
+    Ds = hc_inputs.batched_dims(96)
+    print(f"persistent pairs f64 config mix {len(Ds)} pairs", flush=True)
+    plan = hc.BatchedPlan(Ds, torch.float64, persistent_pairs=True)
+    xs = [hc_inputs.pair_masses(int(D), hc_inputs.W_BATCHED, i)[0] for i, D in enumerate(Ds)]
+    ys = [hc_inputs.pair_masses(int(D), hc_inputs.W_BATCHED, i)[1] for i, D in enumerate(Ds)]
+    Z = run_plan(plan, xs, ys)
+    check_pairs(plan, Ds, xs, ys, Z)
+    groups = {g["D"]: g for g in plan.schedule["groups"]}
+    assert groups[14]["inverse_groups"] == ["4+2"] and groups[14]["forward_groups"] == [3, 3]
+    assert groups[8]["inverse_groups"] == [] and groups[8]["K"] == 8
