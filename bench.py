@@ -425,7 +425,8 @@ def run_batched(args, torch, hc, steps=None, warmup=None):
     """4096 pairs with D drawn uniformly from {6, ..., 14}: one graph launch of
     the batched plan per step, in float64 and float32; compared with a loop
     of single-pair calls, and (float32) against the float64 oracle on a
-    sample of pairs."""
+    sample of pairs.  The same batch is also timed as one persistent kernel
+    launch (a workgroup per pair) and compared with the graph bit for bit."""
     import numpy as np
 
     import hc_inputs
@@ -480,9 +481,24 @@ def run_batched(args, torch, hc, steps=None, warmup=None):
         res["sample_pairs_bitwise_equal_oracle"] = ok
         if name == "f32":
             res["f32_vs_f64_oracle_max_rel_err"] = worst32
+        del Zl, wsl
+        # the same batch as one persistent kernel launch, a workgroup per pair
+        pplan = hc.BatchedPlan(Ds, tdt, persistent_pairs=True)
+        Zp = torch.empty_like(Z)
+        wsp = torch.empty(max(pplan.workspace_bytes, 1), dtype=torch.uint8, device=dev)
+        ms_p, _, stats_p = time_steps(lambda: pplan.run(X, Y, out=Zp, workspace=wsp), steps, warmup, torch)
+        pplan.check()
+        iv = torch.int64 if name == "f64" else torch.int32
+        res["persistent_pairs"] = {
+            "ms_per_step": round(ms_p, 3), "pairs_per_s": round(len(Ds) / (ms_p / 1e3), 1),
+            "outputs_per_s": round(out["outputs"] / (ms_p / 1e3), 1), "grid": pplan.schedule["grid"],
+            "workgroups_per_cu": pplan.schedule["workgroups_per_cu"],
+            "bitwise_equal_to_graph": bool(torch.equal(Zp.view(iv), Z.view(iv))), "kernels": kernel_table(stats_p, steps)}
         out[name] = res
-        log(f"batched {name}: {ms:.3f} ms/step, loop of single calls {ms_loop:.3f} ms, sample parity {ok}")
-        del X, Y, Z, ws, Zl, wsl
+        log(f"batched {name}: {ms:.3f} ms/step, loop of single calls {ms_loop:.3f} ms, sample parity {ok}; "
+            f"one persistent launch {ms_p:.3f} ms/step")
+        del X, Y, Z, ws, Zp, wsp
+        pplan.close()
         plan.close()
         torch.cuda.empty_cache()
     return out

@@ -124,11 +124,14 @@ int run_backward(const Plan& P, const T* x, const T* y, const T* gz, uint64_t gz
 // Threads per workgroup: nine waves, one per digit pair of the two wave
 // axes of its LDS passes.
 constexpr int PAIR_NT = 576;
+// Largest fused depth of its tiles: 9 for 4-byte elements (one 3^9 tile in
+// LDS), 8 for 8-byte elements (three 3^8 tiles side by side in LDS).
+__host__ __device__ constexpr int pair_kmax(size_t elem_size) { return elem_size == 4 ? 9 : 8; }
 
 // Schedule of one pair of dimension D in the persistent kernel: fused depth
-// K (K = D when D fits one tile, else the largest tile), p = D - K outer axes,
-// the outer forward groups (ascending) and the outer inverse passes in
-// execution order (axes [inv_a, inv_a + inv_r + inv_w), inv_r in registers).
+// K = min(D, pair_kmax), p = D - K outer axes, the outer forward groups
+// (ascending) and the outer inverse passes in execution order (axes
+// [inv_a, inv_a + inv_r + inv_w), inv_r of them in registers).
 struct PairPlan {
     uint8_t K = 0, p = 0, n_fwd = 0, n_inv = 0;
     uint8_t fwd[4] = {0, 0, 0, 0};

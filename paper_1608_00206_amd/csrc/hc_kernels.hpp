@@ -90,20 +90,24 @@ struct FusedCfg {
     static constexpr int LDS = cmax(N3, FWD_LDS);
 };
 
-// Forward half shared by the fused forward and the fused adjoint: loads the
-// two rows and applies F on groups C and B, leaving x and y in R2 with layout
-// [bA][gC][gB] (so that P3's reads are consecutive across lanes).
+// Forward half shared by the fused forward and the fused adjoint: takes the
+// two rows from registers and applies F on groups C and B, leaving x and y in
+// R2 with layout [bA][gC][gB] (so that P3's reads are consecutive across
+// lanes).
 // Rows held in registers (entries tid, tid + NT, ... of each): the adjoint
 // tile loads them before its w row, so that both loads are in flight at once.
+// `tid` is the thread's index among the NT threads that share the tile
+// (threadIdx.x unless a workgroup splits into several tile groups).
 template <typename T, int K, int NT>
 struct RowRegs {
     static constexpr int N = (FusedCfg<K>::N2 + NT - 1) / NT;
     T x[N], y[N];
-    __device__ __forceinline__ void load(const T* __restrict__ xr, const T* __restrict__ yr)
+    __device__ __forceinline__ void load(const T* __restrict__ xr, const T* __restrict__ yr,
+                                         int tid = (int)threadIdx.x)
     {
 #pragma unroll
         for (int j = 0; j < N; ++j) {
-            const int i = (int)threadIdx.x + j * NT;
+            const int i = tid + j * NT;
             if (i < FusedCfg<K>::N2) {
                 x[j] = xr[i];
                 y[j] = yr[i];
@@ -113,22 +117,10 @@ struct RowRegs {
 };
 
 template <typename T, int K, int NT>
-__device__ __forceinline__ void fused_forward_cb_from(const RowRegs<T, K, NT>& rows, T* R0, T* R1, T* R2);
-
-template <typename T, int K, int NT>
-__device__ __forceinline__ void fused_forward_cb(const T* __restrict__ xr, const T* __restrict__ yr,
-                                                 T* R0, T* R1, T* R2)
-{
-    RowRegs<T, K, NT> rows;
-    rows.load(xr, yr);
-    fused_forward_cb_from<T, K, NT>(rows, R0, R1, R2);
-}
-
-template <typename T, int K, int NT>
-__device__ __forceinline__ void fused_forward_cb_from(const RowRegs<T, K, NT>& rows, T* R0, T* R1, T* R2)
+__device__ __forceinline__ void fused_forward_cb_from(const RowRegs<T, K, NT>& rows, T* R0, T* R1, T* R2,
+                                                      int tid = (int)threadIdx.x)
 {
     using C = FusedCfg<K>;
-    const int tid = threadIdx.x;
 #pragma unroll
     for (int j = 0; j < RowRegs<T, K, NT>::N; ++j) {
         const int i = tid + j * NT;
@@ -166,12 +158,12 @@ __device__ __forceinline__ void fused_forward_cb_from(const RowRegs<T, K, NT>& r
     lds_barrier();
 }
 
-// One fused tile: rows xr, yr (2^K each) -> zr (3^K).  lds holds
-// FusedCfg<K>::LDS elements; the caller separates two tiles that reuse it by
-// an lds_barrier().  NT threads take part.
+// One fused tile from rows already loaded into registers -> zr (3^K).  lds
+// holds FusedCfg<K>::LDS elements; the caller separates two tiles that reuse
+// it by an lds_barrier().  NT threads take part, `tid` = 0 .. NT-1 among them.
 template <typename T, int K, int NT>
-__device__ __forceinline__ void fused_tile(const T* __restrict__ xr, const T* __restrict__ yr, T* __restrict__ zr,
-                                           T* lds)
+__device__ __forceinline__ void fused_tile_from(const RowRegs<T, K, NT>& rows, T* __restrict__ zr, T* lds,
+                                                int tid)
 {
     using C = FusedCfg<K>;
     T* R0 = lds;
@@ -180,8 +172,7 @@ __device__ __forceinline__ void fused_tile(const T* __restrict__ xr, const T* __
     T* Z = lds;  // aliases R0..R2; written only after R2 has been read
     constexpr int N3I = C::tC * C::tB;  // P3 items
     constexpr int IPT = (N3I + NT - 1) / NT;
-    const int tid = threadIdx.x;
-    fused_forward_cb<T, K, NT>(xr, yr, R0, R1, R2);
+    fused_forward_cb_from<T, K, NT>(rows, R0, R1, R2, tid);
     // P3: registers take this thread's R2 columns, then Z may overwrite R2
     T xa[IPT][C::nA], ya[IPT][C::nA];
 #pragma unroll
@@ -240,6 +231,17 @@ __device__ __forceinline__ void fused_tile(const T* __restrict__ xr, const T* __
 #pragma unroll
         for (int gC = 0; gC < C::tC; ++gC) zr[gC * (C::tB * C::tA) + it] = v[gC];
     }
+}
+
+// One fused tile: rows xr, yr (2^K each) -> zr (3^K), all NT threads of the
+// workgroup taking part.
+template <typename T, int K, int NT>
+__device__ __forceinline__ void fused_tile(const T* __restrict__ xr, const T* __restrict__ yr, T* __restrict__ zr,
+                                           T* lds)
+{
+    RowRegs<T, K, NT> rows;
+    rows.load(xr, yr);
+    fused_tile_from<T, K, NT>(rows, zr, lds, (int)threadIdx.x);
 }
 
 template <typename T, int K, int NT>

@@ -29,10 +29,17 @@ template <typename T>
 struct PersistCfg {
     static constexpr int NT = PAIR_NT;
     static constexpr int WAVES = NT / 64;
-    static constexpr int KMAX = sizeof(T) == 4 ? 9 : 8;
-    // one LDS buffer serves the fused tile and the two-axis wave passes
-    static constexpr int LDS = cmax(FusedCfg<KMAX>::LDS, cmax(PassCfg<4, 2, 1>::LDS, PassCfg<3, 2, 1>::LDS));
+    static constexpr int KMAX = pair_kmax(sizeof(T));
+    // 8-byte elements: the fused stage of a pair with outer axes runs three
+    // tiles of 3^8 at once, one per group of three waves (its 3^p tiles split
+    // evenly into three runs).  4-byte elements: one tile of 3^9 at a time
+    // by all nine waves, and two workgroups per CU.
+    static constexpr int GROUPS = sizeof(T) == 4 ? 1 : 3, GNT = NT / GROUPS;
+    static constexpr int TILE_LDS = FusedCfg<KMAX>::LDS;
+    // one LDS buffer serves the three fused tiles and the two-axis wave passes
+    static constexpr int LDS = cmax(GROUPS * TILE_LDS, cmax(PassCfg<4, 2, 1>::LDS, PassCfg<3, 2, 1>::LDS));
     static_assert(PassCfg<4, 2, 1>::WAVES == WAVES && PassCfg<2, 2, 1>::LDS <= LDS, "pass shapes");
+    static_assert(GNT % 64 == 0, "tile groups of whole waves");
 };
 
 __device__ __forceinline__ uint64_t pow3d(int n)
@@ -45,9 +52,11 @@ __device__ __forceinline__ uint64_t pow3d(int n)
 // Full workgroup barrier: orders global memory as well as LDS.
 __device__ __forceinline__ void wg_barrier() { __syncthreads(); }
 
-// The fused tile of a pair with no outer axes (K = D).
+// The fused tile of a pair with no outer axes (K = D).  A function of its
+// own (not inlined): its nine shapes would otherwise add to the register
+// pressure of the kernel's large-pair path.
 template <typename T>
-__device__ __forceinline__ void single_tile(int K, const T* x, const T* y, T* z, T* S)
+__device__ __attribute__((noinline)) void single_tile(int K, const T* x, const T* y, T* z, T* S)
 {
     constexpr int NT = PersistCfg<T>::NT;
     switch (K) {
@@ -63,6 +72,31 @@ __device__ __forceinline__ void single_tile(int K, const T* x, const T* y, T* z,
         default:
             if constexpr (PersistCfg<T>::KMAX >= 9) fused_tile<T, 9, NT>(x, y, z, S);
             break;
+    }
+}
+
+// The fused stage of a pair with p >= 1 outer axes: tile group g (waves
+// 3g .. 3g+2) runs the tiles [g, g + 1) * 3^(p-1) one after another, with the
+// next tile's rows loaded while the current tile is computed.  The groups run
+// the same number of tiles with the same code, so they meet at every barrier.
+template <typename T>
+__device__ __forceinline__ void fused_stage(const T* xt, const T* yt, T* z, int p, int wave, T* S)
+{
+    using C = PersistCfg<T>;
+    constexpr int K = C::KMAX, GNT = C::GNT;
+    const int grp = wave / (C::WAVES / C::GROUPS);
+    const int gtid = (int)threadIdx.x - grp * GNT;
+    T* Sg = S + grp * C::TILE_LDS;
+    const uint32_t per = (uint32_t)(pow3d(p) / C::GROUPS);
+    uint32_t o = (uint32_t)grp * per;
+    const uint32_t end = o + per;
+    RowRegs<T, K, GNT> next;
+    next.load(xt + ((uint64_t)o << K), yt + ((uint64_t)o << K), gtid);
+    for (; o < end; ++o) {
+        const RowRegs<T, K, GNT> cur = next;
+        if (o + 1 < end) next.load(xt + ((uint64_t)(o + 1) << K), yt + ((uint64_t)(o + 1) << K), gtid);
+        lds_barrier();  // the previous tile's reads of S are done
+        fused_tile_from<T, K, GNT>(cur, z + (uint64_t)o * pow3c(K), Sg, gtid);
     }
 }
 
@@ -125,7 +159,6 @@ __device__ __forceinline__ void inverse_pass(int mR, int mW, T* z, uint64_t L, u
 template <typename T>
 __device__ __forceinline__ void run_pair(const PairPlan& pp, int D, const T* x, const T* y, T* z, T* slot, T* S)
 {
-    constexpr int KMAX = PersistCfg<T>::KMAX;
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     if (pp.p == 0) {
         single_tile<T>(pp.K, x, y, z, S);
@@ -152,12 +185,7 @@ __device__ __forceinline__ void run_pair(const PairPlan& pp, int D, const T* x, 
         a += M;
     }
     // fused inner tiles (a pair with outer axes has K = KMAX)
-    const uint32_t n_tiles = (uint32_t)pow3d(pp.p);
-    for (uint32_t o = 0; o < n_tiles; ++o) {
-        lds_barrier();  // the previous tile's reads of S are done
-        fused_tile<T, KMAX, PersistCfg<T>::NT>(xt + ((uint64_t)o << KMAX), yt + ((uint64_t)o << KMAX),
-                                                z + (uint64_t)o * pow3c(KMAX), S);
-    }
+    fused_stage<T>(xt, yt, z, pp.p, wave, S);
     wg_barrier();
     // outer inverse passes, in place
     for (int i = 0; i < pp.n_inv; ++i) {
@@ -167,8 +195,10 @@ __device__ __forceinline__ void run_pair(const PairPlan& pp, int D, const T* x, 
     }
 }
 
+// 4-byte elements: at most 96 registers, so that two workgroups share a CU.
 template <typename T>
-__global__ __launch_bounds__(PAIR_NT) void k_pairs_persistent(const T* __restrict__ x, const T* __restrict__ y,
+__global__ __launch_bounds__(PAIR_NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 5 : 1)))
+void k_pairs_persistent(const T* __restrict__ x, const T* __restrict__ y,
                                                               T* z, T* ws, uint64_t slot_elems,
                                                               const PairTask* __restrict__ tasks,
                                                               const PairPlan* __restrict__ plans, uint32_t n_pairs,
@@ -201,7 +231,7 @@ __global__ __launch_bounds__(PAIR_NT) void k_pairs_persistent(const T* __restric
 PairPlan pair_plan(int D, int dtype)
 {
     PairPlan pp;
-    const int kmax = max_fused_depth(dtype);
+    const int kmax = pair_kmax(dtype_size(dtype));
     const int K = D < kmax ? D : kmax;
     pp.K = (uint8_t)K;
     pp.p = (uint8_t)(D - K);
