@@ -483,7 +483,7 @@ def run_batched(args, torch, hc, steps=None, warmup=None):
             res["f32_vs_f64_oracle_max_rel_err"] = worst32
         del Zl, wsl
         # the same batch as one persistent kernel launch, a workgroup per pair
-        pplan = hc.BatchedPlan(Ds, tdt, persistent_pairs=True)
+        pplan = hc.BatchedPlan(Ds, tdt, tune=True, persistent_pairs=True)
         Zp = torch.empty_like(Z)
         wsp = torch.empty(max(pplan.workspace_bytes, 1), dtype=torch.uint8, device=dev)
         ms_p, _, stats_p = time_steps(lambda: pplan.run(X, Y, out=Zp, workspace=wsp), steps, warmup, torch)
@@ -493,6 +493,7 @@ def run_batched(args, torch, hc, steps=None, warmup=None):
             "ms_per_step": round(ms_p, 3), "pairs_per_s": round(len(Ds) / (ms_p / 1e3), 1),
             "outputs_per_s": round(out["outputs"] / (ms_p / 1e3), 1), "grid": pplan.schedule["grid"],
             "workgroups_per_cu": pplan.schedule["workgroups_per_cu"],
+            "schedule": [[g["D"], g["forward_groups"], g["inverse_groups"]] for g in pplan.schedule["groups"]],
             "bitwise_equal_to_graph": bool(torch.equal(Zp.view(iv), Z.view(iv))), "kernels": kernel_table(stats_p, steps)}
         out[name] = res
         log(f"batched {name}: {ms:.3f} ms/step, loop of single calls {ms_loop:.3f} ms, sample parity {ok}; "

@@ -260,12 +260,14 @@ int hc_convolve_backward(const void* x, const void* y, const void* grad_z,
  * pair) whose workgroups take pairs by ticket from a list sorted by
  * decreasing D and each run the whole single-pair path of their pair (outer
  * forward, fused tiles, outer inverse), separated by workgroup barriers.  No
- * workgroup waits for another.  The schedule per D is fixed (largest fused
- * tile, outer forward groups of at most three axes, outer inverse groups of
- * six axes as 4 + 2, then 3 + 2, 2 + 2 or up to three register axes); the
- * workspace holds one slot per workgroup.  Results are again bitwise those of
- * hc_convolve.  Launches of one plan must not overlap in time (they share
- * the plan's ticket counters as well as its workspace).
+ * workgroup waits for another.  The default schedule per D takes the
+ * largest fused tile (3^9 for float32, else 3^8), outer forward groups of at
+ * most three axes and outer inverse groups of six axes as 4 + 2 (then 3 + 2,
+ * 2 + 2 or up to three register axes); with HC_PLAN_TUNE the autotuner times
+ * smaller groups per D as persistent launches over that D's pairs and keeps
+ * the fastest.  The workspace holds one slot per workgroup.  Results are
+ * again bitwise those of hc_convolve.  Launches of one plan must not overlap
+ * in time (they share the plan's ticket counters as well as its workspace).
  */
 typedef struct hc_plan hc_plan;
 

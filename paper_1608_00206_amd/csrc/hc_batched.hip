@@ -46,6 +46,10 @@ constexpr int MAX_ITEMS = 65535;
 
 }  // namespace
 
+// Entries of a persistent plan's per-D schedule table (batched pairs have
+// D <= 16).
+constexpr int PAIR_TABLE = 17;
+
 struct hc_plan {
     int dtype = 0;
     size_t es = 0;
@@ -71,6 +75,7 @@ struct hc_plan {
     int per_cu = 0;                     // resident workgroups per CU
     uint64_t slot_elems = 0;            // workspace elements per workgroup
     std::vector<hc::PairPlan> plans;    // by D
+    std::vector<int> fwd_max, inv_max;  // by D: the schedule knobs the plans were made with
     hc::PairTask* d_tasks = nullptr;    // ticket order: decreasing D
     hc::PairPlan* d_plans = nullptr;
     uint32_t* d_counters = nullptr;     // ticket counter, workgroups finished
@@ -164,9 +169,7 @@ static int finalize(hc_plan* pl)
 // decreasing D, ties in pair order), the workspace slots and the counters.
 static int finalize_pairs(hc_plan* pl)
 {
-    constexpr int ND = 17;  // batched pairs have D <= 16
-    pl->plans.assign(ND, PairPlan());
-    for (int D = 0; D < ND; ++D) pl->plans[D] = pair_plan(D, pl->dtype);
+    constexpr int ND = PAIR_TABLE;
     std::vector<int> order(pl->n_pairs);
     for (int i = 0; i < pl->n_pairs; ++i) order[i] = i;
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return pl->Ds[a] > pl->Ds[b]; });
@@ -182,8 +185,6 @@ static int finalize_pairs(hc_plan* pl)
         pl->slot_elems = std::max<uint64_t>(pl->slot_elems, pair_slot_elems(pl->plans[D]));
         pl->alg_bytes += pair_alg_bytes(pl->plans[D], D, pl->es);
     }
-    int rc = pairs_per_cu(pl->dtype, &pl->per_cu);
-    if (rc != HC_OK) return rc;
     const uint64_t g = std::min<uint64_t>((uint64_t)pl->n_pairs, (uint64_t)pl->cus * pl->per_cu);
     pl->grid = (uint32_t)(g ? g : 1);
     pl->ws_bytes = pl->slot_elems ? ((pl->grid * pl->slot_elems * pl->es + 255) & ~255ull) : 0;
@@ -433,6 +434,209 @@ static int tune_group_t(hc_plan* pl, Group& g)
     return rc;
 }
 
+// Persistent plans: for every D with outer axes, candidate schedules (outer
+// forward groups of at most 3 or 2 axes, outer inverse groups of at most 6 ..
+// 2 axes) are timed as persistent launches over that D's pairs alone (at
+// most two per resident workgroup), with temporary buffers; all candidates'
+// outputs must agree bit for bit.  Cache lines: "p1:dtype:D:pairs fwd_max
+// inv_max".
+static std::string pairs_cache_key(int dtype, int D, size_t pairs)
+{
+    return "p1:" + std::to_string(dtype) + ":" + std::to_string(D) + ":" + std::to_string(pairs);
+}
+
+static bool pairs_cache_lookup(const std::string& key, int* fm, int* im)
+{
+    const char* path = getenv("HC_TUNE_CACHE");
+    if (!path) return false;
+    FILE* f = fopen(path, "r");
+    if (!f) return false;
+    char line[512];
+    bool found = false;
+    while (fgets(line, sizeof(line), f)) {
+        char k[256];
+        int a, b;
+        if (sscanf(line, "%255s %d %d", k, &a, &b) == 3 && key == k && a >= 2 && a <= 3 && b >= 2 && b <= 6) {
+            *fm = a;
+            *im = b;
+            found = true;
+        }
+    }
+    fclose(f);
+    return found;
+}
+
+static void pairs_cache_store(const std::string& key, int fm, int im)
+{
+    const char* path = getenv("HC_TUNE_CACHE");
+    if (!path) return;
+    FILE* f = fopen(path, "a");
+    if (!f) return;
+    fprintf(f, "%s %d %d\n", key.c_str(), fm, im);
+    fclose(f);
+}
+
+static bool same_pair_plan(const PairPlan& a, const PairPlan& b)
+{
+    return memcmp(&a, &b, sizeof(PairPlan)) == 0;
+}
+
+template <typename T>
+static int tune_pairs_d(hc_plan* pl, int D, int count)
+{
+    const uint32_t cap = (uint32_t)pl->cus * (uint32_t)pl->per_cu;
+    const int n = (int)std::min<uint64_t>((uint64_t)count, 2ull * cap);
+    const uint32_t grid = (uint32_t)std::min<uint64_t>((uint64_t)n, cap);
+    struct Cand {
+        int fm, im;
+        PairPlan pp;
+    };
+    std::vector<Cand> cands;
+    for (int fm : {3, 2})
+        for (int im : {6, 5, 4, 3, 2}) {
+            const PairPlan pp = pair_plan(D, pl->dtype, fm, im);
+            bool dup = false;
+            for (const Cand& c : cands) dup |= same_pair_plan(c.pp, pp);
+            if (!dup) cands.push_back({fm, im, pp});
+        }
+    if (cands.size() == 1) {  // one outer axis: nothing to choose
+        pl->plans[D] = cands[0].pp;
+        pl->fwd_max[D] = cands[0].fm;
+        pl->inv_max[D] = cands[0].im;
+        return HC_OK;
+    }
+    uint64_t slot = 0;
+    for (const Cand& c : cands) slot = std::max<uint64_t>(slot, pair_slot_elems(c.pp));
+    const uint64_t nx = (uint64_t)n << D, nz = (uint64_t)n * pow3u(D);
+    std::vector<PairTask> tasks(n);
+    for (int i = 0; i < n; ++i) {
+        tasks[i].x_off = (uint64_t)i << D;
+        tasks[i].z_off = (uint64_t)i * pow3u(D);
+        tasks[i].D = (uint32_t)D;
+    }
+    T *x = nullptr, *y = nullptr, *z = nullptr, *ws = nullptr;
+    PairTask* d_tasks = nullptr;
+    PairPlan* d_tab = nullptr;
+    uint32_t* d_cnt = nullptr;
+    unsigned long long* dg = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipMalloc(&x, nx * sizeof(T));
+    if (e == hipSuccess) e = hipMalloc(&y, nx * sizeof(T));
+    if (e == hipSuccess) e = hipMalloc(&z, nz * sizeof(T));
+    if (e == hipSuccess) e = hipMalloc(&ws, std::max<uint64_t>(grid * slot * sizeof(T), 16));
+    if (e == hipSuccess) e = hipMalloc(&d_tasks, n * sizeof(PairTask));
+    if (e == hipSuccess) e = hipMalloc(&d_tab, PAIR_TABLE * sizeof(PairPlan));
+    if (e == hipSuccess) e = hipMalloc(&d_cnt, 2 * sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMalloc(&dg, sizeof(unsigned long long));
+    if (e == hipSuccess) e = hipMemcpy(d_tasks, tasks.data(), n * sizeof(PairTask), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(d_cnt, 0, 2 * sizeof(uint32_t));
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    int rc = e == hipSuccess ? HC_OK : hip_fail(e, "autotuner buffers");
+    if (rc == HC_OK) {
+        // inexact inputs in floating point, so the digests compare evaluation orders too
+        std::vector<T> hx(nx);
+        for (uint64_t i = 0; i < nx; ++i) {
+            const int v = (int)((i * 2654435761ull >> 7) % 1000);
+            hx[i] = std::is_integral<T>::value ? (T)(v % 16) : (T)(v / 7.0);
+        }
+        e = hipMemcpy(x, hx.data(), nx * sizeof(T), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(y, hx.data(), nx * sizeof(T), hipMemcpyHostToDevice);
+        if (e != hipSuccess) rc = hip_fail(e, "autotuner inputs");
+    }
+    float best_ms = 1e30f;
+    int best = 0;
+    unsigned long long ref = 0;
+    for (size_t c = 0; rc == HC_OK && c < cands.size(); ++c) {
+        std::vector<PairPlan> tab = pl->plans;
+        tab[D] = cands[c].pp;
+        e = hipMemcpy(d_tab, tab.data(), PAIR_TABLE * sizeof(PairPlan), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            rc = hip_fail(e, "autotuner table");
+            break;
+        }
+        auto run = [&]() {
+            return launch_pairs_persistent(pl->dtype, x, y, z, ws, slot, d_tasks, d_tab, (uint32_t)n, d_cnt, grid,
+                                           nullptr);
+        };
+        rc = run();  // warm-up
+        if (rc == HC_OK) (void)hipEventRecord(e0, nullptr);
+        for (int k = 0; k < 3 && rc == HC_OK; ++k) rc = run();
+        if (rc != HC_OK) break;
+        (void)hipEventRecord(e1, nullptr);
+        e = hipEventSynchronize(e1);
+        float ms = 0;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        unsigned long long digest = 0;
+        if (e == hipSuccess) e = hipMemset(dg, 0, sizeof(digest));
+        if (e == hipSuccess) {
+            k_digest<<<1024, 256>>>((const uint32_t*)z, nz * sizeof(T) / 4, dg);
+            e = hipMemcpy(&digest, dg, sizeof(digest), hipMemcpyDeviceToHost);
+        }
+        if (e != hipSuccess) {
+            rc = hip_fail(e, "autotuner timing");
+            break;
+        }
+        if (c == 0) ref = digest;
+        else if (digest != ref) {
+            rc = fail(HC_ERR_HIP, "autotuner: persistent schedule %zu for D=%d produced different bits", c, D);
+            break;
+        }
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = (int)c;
+        }
+    }
+    if (rc == HC_OK) {
+        pl->plans[D] = cands[best].pp;
+        pl->fwd_max[D] = cands[best].fm;
+        pl->inv_max[D] = cands[best].im;
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(x);
+    (void)hipFree(y);
+    (void)hipFree(z);
+    (void)hipFree(ws);
+    (void)hipFree(d_tasks);
+    (void)hipFree(d_tab);
+    (void)hipFree(d_cnt);
+    (void)hipFree(dg);
+    return rc;
+}
+
+// Default per-D schedules of a persistent plan, then (HC_PLAN_TUNE) the
+// autotuner's choice for every D with outer axes, largest D first.
+static int plan_pairs(hc_plan* pl)
+{
+    pl->plans.assign(PAIR_TABLE, PairPlan());
+    pl->fwd_max.assign(PAIR_TABLE, 3);
+    pl->inv_max.assign(PAIR_TABLE, 6);
+    for (int D = 0; D < PAIR_TABLE; ++D) pl->plans[D] = pair_plan(D, pl->dtype);
+    int rc = pairs_per_cu(pl->dtype, &pl->per_cu);
+    if (rc != HC_OK || !(pl->flags & HC_PLAN_TUNE)) return rc;
+    for (int D = PAIR_TABLE - 1; D >= 0; --D) {
+        const int count = (int)std::count(pl->Ds.begin(), pl->Ds.end(), D);
+        if (count == 0 || pl->plans[D].p == 0) continue;
+        const std::string key = pairs_cache_key(pl->dtype, D, count);
+        int fm = 3, im = 6;
+        if (pairs_cache_lookup(key, &fm, &im)) {
+            pl->plans[D] = pair_plan(D, pl->dtype, fm, im);
+            pl->fwd_max[D] = fm;
+            pl->inv_max[D] = im;
+            continue;
+        }
+        switch (pl->dtype) {
+            case HC_F64: rc = tune_pairs_d<double>(pl, D, count); break;
+            case HC_F32: rc = tune_pairs_d<float>(pl, D, count); break;
+            default: rc = tune_pairs_d<uint64_t>(pl, D, count); break;
+        }
+        if (rc != HC_OK) return rc;
+        pairs_cache_store(key, pl->fwd_max[D], pl->inv_max[D]);
+    }
+    return HC_OK;
+}
+
 static int tune(hc_plan* pl)
 {
     for (Group& g : pl->groups) {
@@ -518,7 +722,8 @@ int hc_plan_create_batched(const int* Ds, int n_pairs, int dtype, unsigned flags
     if (e == hipSuccess) e = hipEventCreateWithFlags(&pl->launched, hipEventDisableTiming);
     rc = e == hipSuccess ? HC_OK : hip_fail(e, "plan stream");
     if (rc == HC_OK && pl->pairs) {
-        rc = finalize_pairs(pl);
+        rc = plan_pairs(pl);
+        if (rc == HC_OK) rc = finalize_pairs(pl);
     } else if (rc == HC_OK) {
         if (flags & HC_PLAN_TUNE) rc = tune(pl);
         else

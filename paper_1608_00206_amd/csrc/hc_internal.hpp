@@ -146,7 +146,10 @@ struct PairTask {
     uint32_t D = 0, pad = 0;
 };
 
-PairPlan pair_plan(int D, int dtype);
+// The default schedule takes forward groups of at most 3 axes and inverse
+// groups of at most 6; the autotuner also tries smaller groups (fwd_max in
+// {2, 3}, inv_max in 2..6).
+PairPlan pair_plan(int D, int dtype, int fwd_max = 3, int inv_max = 6);
 uint64_t pair_slot_elems(const PairPlan& pp);  // workspace elements per workgroup
 double pair_alg_bytes(const PairPlan& pp, int D, size_t es);
 int pairs_per_cu(int dtype, int* per_cu);      // resident workgroups per CU

@@ -228,40 +228,43 @@ void k_pairs_persistent(const T* __restrict__ x, const T* __restrict__ y,
 }
 
 // ------------------------------------------------------------------ host
-PairPlan pair_plan(int D, int dtype)
+PairPlan pair_plan(int D, int dtype, int fwd_max, int inv_max)
 {
     PairPlan pp;
     const int kmax = pair_kmax(dtype_size(dtype));
     const int K = D < kmax ? D : kmax;
+    fwd_max = fwd_max < 2 ? 2 : (fwd_max > 3 ? 3 : fwd_max);
+    inv_max = inv_max < 2 ? 2 : (inv_max > 6 ? 6 : inv_max);
     pp.K = (uint8_t)K;
     pp.p = (uint8_t)(D - K);
     if (pp.p == 0) return pp;
-    // outer forward groups of at most three axes, balanced; stage i lands in
-    // x~ when an even number of stages follow it, else in the staging region
-    const int n = (pp.p + 2) / 3;
-    int left = pp.p, a = 0;
+    // outer forward groups of at most fwd_max axes, balanced; stage i lands
+    // in x~ when an even number of stages follow it, else in the staging region
+    const int n = (pp.p + fwd_max - 1) / fwd_max;
+    int left = pp.p, done = 0;
     for (int i = 0; i < n; ++i) {
         const int M = (left + (n - i) - 1) / (n - i);
         pp.fwd[i] = (uint8_t)M;
-        a += M;
+        done += M;
         left -= M;
-        const uint64_t e = pow3u(a) << (D - a);
+        const uint64_t e = pow3u(done) << (D - done);
         if (((n - 1 - i) & 1) == 1 && e > pp.tmp_elems) pp.tmp_elems = (uint32_t)e;
     }
     pp.n_fwd = (uint8_t)n;
     pp.xt_elems = (uint32_t)(pow3u(pp.p) << K);
-    // inverse groups from the top: six axes as 4 + 2 (streamed thirds), five
-    // as 3 + 2, four as 2 + 2, up to three in registers only
+    // inverse groups of at most inv_max axes from the top: six axes as 4 + 2
+    // (streamed thirds), five as 3 + 2, four as 2 + 2, up to three in
+    // registers only
     int top = pp.p;
     while (top > 0) {
-        const int m = top < 6 ? top : 6;
-        const int a = top - m;
+        const int m = top < inv_max ? top : inv_max;
+        const int base = top - m;
         const int r = m == 6 ? 4 : (m == 5 ? 3 : (m == 4 ? 2 : m));
-        pp.inv_a[pp.n_inv] = (uint8_t)a;
+        pp.inv_a[pp.n_inv] = (uint8_t)base;
         pp.inv_r[pp.n_inv] = (uint8_t)r;
         pp.inv_w[pp.n_inv] = (uint8_t)(m - r);
         ++pp.n_inv;
-        top = a;
+        top = base;
     }
     return pp;
 }
