@@ -220,3 +220,19 @@ def test_persistent_pairs_tuned_and_cached(tmp_path, monkeypatch):
     Zt = run_plan(plan, xs, ys)
     pins.assert_bitwise(Zt, run_plan(default, xs, ys), "tuned vs default")
     check_pairs(plan, Ds, xs, ys, Zt)
+
+
+@pytest.mark.parametrize("Ds", [[16], [0], [0, 0, 0], [8, 8], [9]])
+def test_persistent_pairs_edge_batches(Ds):
+    """One pair (a grid of one workgroup), pairs that need no workspace, the
+    largest D alone: bitwise equal to single-pair calls."""
+    print(f"persistent pairs f64 edge Ds={Ds}", flush=True)
+    plan = hc.BatchedPlan(Ds, torch.float64, persistent_pairs=True)
+    assert 1 <= plan.schedule["grid"] <= len(Ds)
+    assert (plan.workspace_bytes == 0) == all(D <= 8 for D in Ds)
+    xs, ys = packed_inputs(Ds, np.float64, seed=15)
+    Z = run_plan(plan, xs, ys)
+    for i, D in enumerate(Ds):
+        z1 = hc.convolve(torch.from_numpy(xs[i]).to(DEV), torch.from_numpy(ys[i]).to(DEV)).cpu().numpy()
+        pins.assert_bitwise(Z[plan.z_offsets[i]:plan.z_offsets[i + 1]], z1, f"pair {i} D={D}")
+    plan.close()
