@@ -36,7 +36,8 @@ struct PersistCfg {
     // by all nine waves, and two workgroups per CU.
     static constexpr int GROUPS = sizeof(T) == 4 ? 1 : 3, GNT = NT / GROUPS;
     static constexpr int TILE_LDS = FusedCfg<KMAX>::LDS;
-    // one LDS buffer serves the three fused tiles and the two-axis wave passes
+    // one LDS buffer serves the fused tiles of all groups and the two-axis
+    // wave passes
     static constexpr int LDS = cmax(GROUPS * TILE_LDS, cmax(PassCfg<4, 2, 1>::LDS, PassCfg<3, 2, 1>::LDS));
     static_assert(PassCfg<4, 2, 1>::WAVES == WAVES && PassCfg<2, 2, 1>::LDS <= LDS, "pass shapes");
     static_assert(GNT % 64 == 0, "tile groups of whole waves");
@@ -53,8 +54,8 @@ __device__ __forceinline__ uint64_t pow3d(int n)
 __device__ __forceinline__ void wg_barrier() { __syncthreads(); }
 
 // The fused tile of a pair with no outer axes (K = D).  A function of its
-// own (not inlined): its nine shapes would otherwise add to the register
-// pressure of the kernel's large-pair path.
+// own (not inlined): its shapes K = 0 .. KMAX would otherwise add to the
+// register pressure of the kernel's large-pair path.
 template <typename T>
 __device__ __attribute__((noinline)) void single_tile(int K, const T* x, const T* y, T* z, T* S)
 {
