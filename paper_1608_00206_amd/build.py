@@ -36,6 +36,8 @@ HIPCC_FLAGS = [
     "-Wall",
     "-Wno-unused-result",
 ]
+# roctx ranges around the entry points (rocprofv3 --marker-trace)
+LINK_FLAGS = ["-lrocprofiler-sdk-roctx"]
 
 
 def hipcc() -> str:
@@ -48,7 +50,7 @@ def build(verbose: bool = False) -> str:
     """Compile libhc.so (always recompiles)."""
     tmp = LIB + ".tmp"
     cmd = [hipcc(), *HIPCC_FLAGS, "-I", os.path.join(ROOT, "include"), "-I", CSRC,
-           "-o", tmp, *SOURCES]
+           "-o", tmp, *SOURCES, *LINK_FLAGS]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)

@@ -15,10 +15,45 @@
 #include <type_traits>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "hc_internal.hpp"
 #include "hc_kernels.hpp"
 
 namespace hc {
+
+// ------------------------------------------------------- logging, ranges
+bool log_on()
+{
+    static const bool on = [] {
+        const char* s = getenv("HC_LOG");
+        return s && *s && strcmp(s, "0") != 0;
+    }();
+    return on;
+}
+
+void hc_log(const char* fmt, ...)
+{
+    if (!log_on()) return;
+    char buf[8192];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    fprintf(stderr, "[hc] %s\n", buf);
+}
+
+TraceRange::TraceRange(const char* fmt, ...)
+{
+    char buf[160];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    roctxRangePushA(buf);
+}
+
+TraceRange::~TraceRange() { roctxRangePop(); }
 
 // ------------------------------------------------------------------ errors
 static thread_local std::string g_last_error;
@@ -728,6 +763,7 @@ size_t hc_backward_workspace_bytes(int D, int dtype, int batch)
 int hc_convolve_batch(const void* x, const void* y, void* z, int D, int dtype, int batch, void* workspace,
                       size_t workspace_bytes, hipStream_t stream)
 {
+    TraceRange range("hc_convolve_batch D=%d dtype=%d batch=%d", D, dtype, batch);
     return convolve_batch_last(x, y, z, D, dtype, batch, workspace, workspace_bytes, stream, nullptr);
 }
 
@@ -785,6 +821,7 @@ int hc_convolve_backward_batch(const void* x, const void* y, const void* grad_z,
                                void* grad_x, void* grad_y, int D, int dtype, int batch, void* workspace,
                                size_t workspace_bytes, hipStream_t stream)
 {
+    TraceRange range("hc_convolve_backward_batch D=%d dtype=%d batch=%d", D, dtype, batch);
     g_last_error.clear();
     if (!x || !y || !grad_z) return fail(HC_ERR_INVALID_ARG, "x, y and grad_z must be non-null");
     if (!grad_x && !grad_y) return fail(HC_ERR_INVALID_ARG, "at least one of grad_x, grad_y is required");

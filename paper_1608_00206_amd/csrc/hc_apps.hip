@@ -533,6 +533,7 @@ size_t hc_carryfree_workspace_bytes(uint64_t n, int dtype)
 int hc_carryfree_convolve(const void* x, const void* y, uint64_t n, void* z, int dtype, void* workspace,
                           size_t workspace_bytes, hipStream_t stream)
 {
+    TraceRange range("hc_carryfree_convolve n=%llu dtype=%d", (unsigned long long)n, dtype);
     if (!x || !y || !z) return fail(HC_ERR_INVALID_ARG, "x, y and z must be non-null");
     const int D = carryfree_dim(n);
     if (D < 0) return fail(HC_ERR_D_RANGE, "length %llu outside [1, 2^%d]", (unsigned long long)n, HC_MAX_D);
@@ -586,6 +587,7 @@ size_t hc_difference_workspace_bytes(int D, int dtype, int batch)
 int hc_difference_batch(const void* x, const void* y, void* z, int D, int dtype, int batch, void* workspace,
                         size_t workspace_bytes, hipStream_t stream)
 {
+    TraceRange range("hc_difference_batch D=%d dtype=%d batch=%d", D, dtype, batch);
     if (!x || !y || !z) return fail(HC_ERR_INVALID_ARG, "x, y and z must be non-null");
     if (D < 0 || D > HC_MAX_D) return fail(HC_ERR_D_RANGE, "D=%d outside [0, %d]", D, HC_MAX_D);
     const size_t es = dtype_size(dtype);
@@ -628,6 +630,7 @@ size_t hc_maxconv_workspace_bytes(int D, int dtype, int batch)
 int hc_maxconv_pnorm_batch(const void* x, const void* y, void* z, int D, int dtype, int batch, double p,
                            unsigned flags, void* workspace, size_t workspace_bytes, hipStream_t stream)
 {
+    TraceRange range("hc_maxconv_pnorm_batch D=%d dtype=%d batch=%d p=%g", D, dtype, batch, p);
     if (!x || !y || !z) return fail(HC_ERR_INVALID_ARG, "x, y and z must be non-null");
     if (D < 0 || D > HC_MAX_D) return fail(HC_ERR_D_RANGE, "D=%d outside [0, %d]", D, HC_MAX_D);
     if (dtype != HC_F64 && dtype != HC_F32)

@@ -391,6 +391,8 @@ static int tune_group_t(hc_plan* pl, Group& g)
             he = hipMemcpy(&digest, dg, sizeof(digest), hipMemcpyDeviceToHost);
         }
         if (he != hipSuccess) return hip_fail(he, "autotuner digest");
+        hc_log("tune graph D=%d items=%d: K=%d inv_reg=%d inv_max=%d fused_threads=%d column_groups=%d: %.4f ms", D,
+               n, P.K, o.inv_reg, o.inv_group_max, P.fused_nt, P.reg_cw, ms / 3);
         if (!have_ref) {
             ref = digest;
             have_ref = true;
@@ -577,6 +579,8 @@ static int tune_pairs_d(hc_plan* pl, int D, int count)
             rc = hip_fail(e, "autotuner timing");
             break;
         }
+        hc_log("tune persistent D=%d pairs=%d: forward groups <= %d, inverse groups <= %d: %.4f ms", D, n,
+               cands[c].fm, cands[c].im, ms / 3);
         if (c == 0) ref = digest;
         else if (digest != ref) {
             rc = fail(HC_ERR_HIP, "autotuner: persistent schedule %zu for D=%d produced different bits", c, D);
@@ -703,6 +707,7 @@ extern "C" {
 
 int hc_plan_create_batched(const int* Ds, int n_pairs, int dtype, unsigned flags, hc_plan** out)
 {
+    TraceRange range("hc_plan_create_batched pairs=%d dtype=%d flags=%u", n_pairs, dtype, flags);
     if (!out) return fail(HC_ERR_INVALID_ARG, "out required");
     *out = nullptr;
     int rc = check_pairs(Ds, n_pairs, dtype, flags);
@@ -734,6 +739,10 @@ int hc_plan_create_batched(const int* Ds, int n_pairs, int dtype, unsigned flags
         destroy(pl);
         return rc;
     }
+    if (log_on()) {
+        std::string d(16384, '\0');
+        if (hc_plan_describe(pl, &d[0], d.size()) == HC_OK) hc_log("plan: %s", d.c_str());
+    }
     *out = pl;
     return HC_OK;
 }
@@ -757,6 +766,7 @@ int hc_plan_layout(const hc_plan* plan, uint64_t* x_offsets, uint64_t* z_offsets
 int hc_plan_execute(hc_plan* plan, const void* x, const void* y, void* z, void* workspace, size_t workspace_bytes,
                     hipStream_t stream)
 {
+    TraceRange range("hc_plan_execute pairs=%d", plan ? plan->n_pairs : 0);
     if (!plan || !x || !y || !z) return fail(HC_ERR_INVALID_ARG, "plan, x, y and z are required");
     if (misaligned(x, plan->es) || misaligned(y, plan->es) || misaligned(z, plan->es) || misaligned(workspace, 16))
         return fail(HC_ERR_MISALIGNED, "data must be aligned to the element size, the workspace to 16 bytes");

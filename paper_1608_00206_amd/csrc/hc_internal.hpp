@@ -71,6 +71,21 @@ class CaptureScope {
     CaptureScope& operator=(const CaptureScope&) = delete;
 };
 
+// A roctx range around one entry point (shown by rocprofv3 --marker-trace;
+// a plain call when no tool listens).
+class TraceRange {
+  public:
+    explicit TraceRange(const char* fmt, ...);
+    ~TraceRange();
+    TraceRange(const TraceRange&) = delete;
+    TraceRange& operator=(const TraceRange&) = delete;
+};
+
+// Plan and autotuner decisions on stderr when the environment variable
+// HC_LOG is set (to anything but 0).
+bool log_on();
+void hc_log(const char* fmt, ...);
+
 // Short element-type name for profiler labels.
 template <typename T>
 const char* tname()

@@ -727,6 +727,7 @@ size_t hc_sum3_workspace_bytes(int D, int dtype, int batch)
 int hc_sum3_batch(const void* x1, const void* x2, const void* x3, void* z, int D, int dtype, int batch,
                   void* workspace, size_t workspace_bytes, hipStream_t stream)
 {
+    TraceRange range("hc_sum3_batch D=%d dtype=%d batch=%d", D, dtype, batch);
     if (!x1 || !x2 || !x3 || !z) return fail(HC_ERR_INVALID_ARG, "x1, x2, x3 and z must be non-null");
     if (D < 0 || D > S3_MAX_D) return fail(HC_ERR_D_RANGE, "D=%d outside [0, %d]", D, S3_MAX_D);
     const size_t es = dtype_size(dtype);

@@ -594,6 +594,7 @@ size_t hc_ternary_workspace_bytes(int D, int dtype, int batch)
 int hc_ternary_convolve_batch(const void* a, const void* b, void* z, int D, int dtype, int batch, void* workspace,
                               size_t workspace_bytes, hipStream_t stream)
 {
+    TraceRange range("hc_ternary_convolve_batch D=%d dtype=%d batch=%d", D, dtype, batch);
     if (!a || !b || !z) return fail(HC_ERR_INVALID_ARG, "a, b and z must be non-null");
     if (D < 0 || D > TN_MAX_D) return fail(HC_ERR_D_RANGE, "D=%d outside [0, %d]", D, TN_MAX_D);
     const size_t es = dtype_size(dtype);

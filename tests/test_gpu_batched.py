@@ -236,3 +236,22 @@ def test_persistent_pairs_edge_batches(Ds):
         z1 = hc.convolve(torch.from_numpy(xs[i]).to(DEV), torch.from_numpy(ys[i]).to(DEV)).cpu().numpy()
         pins.assert_bitwise(Z[plan.z_offsets[i]:plan.z_offsets[i + 1]], z1, f"pair {i} D={D}")
     plan.close()
+
+
+def test_plan_log_on_stderr():
+    """HC_LOG=1 prints the plan (and the tuner's candidates) on stderr; the
+    library reads the variable once, so this runs in a child process."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = ("import torch, paper_1608_00206_amd as hc; "
+            "hc.BatchedPlan([3, 9, 9], torch.float64, tune=True, persistent_pairs=True).close(); "
+            "hc.BatchedPlan([3, 10], torch.float64).close()")
+    env = dict(os.environ, HC_LOG="1", PYTHONPATH=root)
+    env.pop("HC_TUNE_CACHE", None)
+    r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=120, cwd=root)
+    assert r.returncode == 0, r.stderr[-2000:]
+    lines = [l for l in r.stderr.splitlines() if l.startswith("[hc] ")]
+    assert sum(1 for l in lines if l.startswith('[hc] plan: {"mode": "persistent_pairs"')) == 1
+    assert sum(1 for l in lines if l.startswith('[hc] plan: {"mode": "graph"')) == 1
