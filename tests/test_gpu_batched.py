@@ -144,7 +144,7 @@ def test_persistent_pairs_match_oracle(dtype):
     plan.close()
 
 
-@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("dtype", [np.float64, np.float32, np.int64])
 def test_persistent_pairs_largest_d_equal_single_calls(dtype):
     """D = 15 and 16: three outer forward groups and two inverse passes;
     bitwise equal to single-pair calls."""
@@ -202,21 +202,24 @@ def test_persistent_pairs_config_mix():
     assert groups[8]["inverse_groups"] == [] and groups[8]["K"] == 8
 
 
-def test_persistent_pairs_tuned_and_cached(tmp_path, monkeypatch):
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_persistent_pairs_tuned_and_cached(dtype, tmp_path, monkeypatch):
     """The autotuner of persistent plans: every candidate schedule agrees
     bitwise (else plan creation fails), the choice is cached, and the tuned
     plan gives the default plan's bits."""
     monkeypatch.setenv("HC_TUNE_CACHE", str(tmp_path / "tune.txt"))
     Ds = [14, 9, 12, 13, 7, 10, 11, 14, 13]
-    print(f"persistent pairs tuned f64 Ds={Ds}", flush=True)
-    plan = hc.BatchedPlan(Ds, torch.float64, tune=True, persistent_pairs=True)
+    tdt = NP2T[np.dtype(dtype)]
+    print(f"persistent pairs tuned {np.dtype(dtype).name} Ds={Ds}", flush=True)
+    plan = hc.BatchedPlan(Ds, tdt, tune=True, persistent_pairs=True)
     assert plan.schedule["tuned"] and plan.schedule["mode"] == "persistent_pairs"
     lines = (tmp_path / "tune.txt").read_text().split()
-    assert sum(1 for w in lines if w.startswith("p1:")) == 6      # D = 9 .. 14 have outer axes
-    again = hc.BatchedPlan(Ds, torch.float64, tune=True, persistent_pairs=True)
+    with_outer = {D for D in Ds if D > (9 if dtype == np.float32 else 8)}
+    assert sum(1 for w in lines if w.startswith("p1:")) == len(with_outer)
+    again = hc.BatchedPlan(Ds, tdt, tune=True, persistent_pairs=True)
     assert again.schedule == plan.schedule
-    default = hc.BatchedPlan(Ds, torch.float64, persistent_pairs=True)
-    xs, ys = packed_inputs(Ds, np.float64, seed=14)
+    default = hc.BatchedPlan(Ds, tdt, persistent_pairs=True)
+    xs, ys = packed_inputs(Ds, dtype, seed=14)
     Zt = run_plan(plan, xs, ys)
     pins.assert_bitwise(Zt, run_plan(default, xs, ys), "tuned vs default")
     check_pairs(plan, Ds, xs, ys, Zt)
