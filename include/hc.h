@@ -280,9 +280,10 @@ typedef struct hc_plan hc_plan;
  * Create a plan for n_pairs pairs with dimensions Ds[0..n_pairs) (host
  * array, 0 <= D <= 16) of `dtype`.  Allocates the plan's device tables and
  * streams on the current device.  With HC_PLAN_TUNE it also allocates
- * temporary buffers and times candidate schedules (this synchronises the
- * device); with the environment variable HC_TUNE_CACHE naming a file, tuned
- * choices are read from and appended to that file.
+ * temporary buffers (outputs of at most 8 GiB: a D whose pairs need more is
+ * timed on part of them) and times candidate schedules (this synchronises
+ * the device); with the environment variable HC_TUNE_CACHE naming a file,
+ * tuned choices are read from and appended to that file.
  * Errors: HC_ERR_INVALID_ARG (null Ds/out, n_pairs < 1, unknown flag,
  * HC_PLAN_PERSISTENT with HC_PLAN_PERSISTENT_PAIRS), HC_ERR_D_RANGE,
  * HC_ERR_UNSUPPORTED, HC_ERR_NO_DEVICE, HC_ERR_HIP.

@@ -320,11 +320,22 @@ static void cache_store(const std::string& key, const PlanOpts& o)
     fclose(f);
 }
 
+// Items the autotuners time at once: the group's own count, but no more
+// than fit a bounded output buffer (large D groups are timed on a part of
+// the group instead of allocating another copy of its whole output).
+constexpr uint64_t TUNE_Z_BYTES = 8ull << 30;
+
+static int tune_items(int items, int D, size_t es)
+{
+    const uint64_t fit = TUNE_Z_BYTES / (pow3u(D) * es);
+    return (int)std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)items, fit));
+}
+
 template <typename T>
 static int tune_group_t(hc_plan* pl, Group& g)
 {
     const int D = g.D;
-    const int n = (int)g.items.size();
+    const int n = tune_items((int)g.items.size(), D, sizeof(T));
     std::vector<PlanOpts> cands;
     const int kmax = max_fused_depth(pl->dtype);
     for (int K : {kmax, kmax - 1, kmax - 2})
@@ -487,7 +498,7 @@ template <typename T>
 static int tune_pairs_d(hc_plan* pl, int D, int count)
 {
     const uint32_t cap = (uint32_t)pl->cus * (uint32_t)pl->per_cu;
-    const int n = (int)std::min<uint64_t>((uint64_t)count, 2ull * cap);
+    const int n = tune_items((int)std::min<uint64_t>((uint64_t)count, 2ull * cap), D, sizeof(T));
     const uint32_t grid = (uint32_t)std::min<uint64_t>((uint64_t)n, cap);
     struct Cand {
         int fm, im;
