@@ -176,6 +176,14 @@ def test_batched_4096_pairs(batched_config, dtype):
         Z = plan.run(X, Y)
         plan.check()
         xo, zo = plan.x_offsets, plan.z_offsets
+        iv = torch.int64 if npdt == np.float64 else torch.int32
+        # the same batch as one persistent launch (tuned): the same bits
+        say(f"batched {dtype}: tuning the persistent plan")
+        with hc.BatchedPlan(Ds, dtype=dtype, tune=True, persistent_pairs=True) as pplan:
+            Zp = pplan.run(X, Y)
+            pplan.check()
+            assert torch.equal(Zp.view(iv), Z.view(iv)), "the persistent launch differs from the graph"
+            del Zp
         # every pair against the single-pair entry point
         for p in range(len(Ds)):
             zs = hc.convolve(X[xo[p]:xo[p + 1]], Y[xo[p]:xo[p + 1]])
