@@ -258,3 +258,38 @@ def test_plan_log_on_stderr():
     lines = [l for l in r.stderr.splitlines() if l.startswith("[hc] ")]
     assert sum(1 for l in lines if l.startswith('[hc] plan: {"mode": "persistent_pairs"')) == 1
     assert sum(1 for l in lines if l.startswith('[hc] plan: {"mode": "graph"')) == 1
+
+
+def test_more_pairs_than_one_launch_holds():
+    """70000 small pairs: the grouped graph splits a D group above 65535
+    items (the grid's y extent) into two launches; the persistent launch
+    takes them all by ticket.  Both against a vectorised definition."""
+    rng = np.random.default_rng(17)
+    Ds = [1] * 66000 + [2] * 4000
+    print(f"batched {len(Ds)} small pairs", flush=True)
+    xs = rng.integers(0, 16, size=sum(2 ** d for d in Ds)).astype(np.int64)
+    ys = rng.integers(0, 16, size=xs.size).astype(np.int64)
+    # the definition, vectorised per D: z[tern(i) + tern(j)] += x[i] y[j]
+    want = []
+    off = 0
+    for D, n in ((1, 66000), (2, 4000)):
+        x = xs[off:off + n * 2 ** D].reshape(n, 2 ** D)
+        y = ys[off:off + n * 2 ** D].reshape(n, 2 ** D)
+        off += n * 2 ** D
+        tern = np.array([int(np.base_repr(i, 2), 3) for i in range(2 ** D)])
+        z = np.zeros((n, 3 ** D), dtype=np.int64)
+        for i in range(2 ** D):
+            for j in range(2 ** D):
+                z[:, tern[i] + tern[j]] += x[:, i] * y[:, j]
+        want.append(z.ravel())
+    want = np.concatenate(want)
+    X = torch.from_numpy(xs).to(DEV)
+    Y = torch.from_numpy(ys).to(DEV)
+    for kw in ({}, {"persistent_pairs": True}):
+        plan = hc.BatchedPlan(Ds, torch.int64, **kw)
+        if not kw:
+            assert [(g["D"], g["items"]) for g in plan.schedule["groups"]] == [(2, 4000), (1, 65535), (1, 465)]
+        Z = plan.run(X, Y)
+        plan.check()
+        pins.assert_bitwise(Z.cpu().numpy(), want, f"70000 pairs {kw}")
+        plan.close()
