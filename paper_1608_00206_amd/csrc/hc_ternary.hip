@@ -126,7 +126,9 @@ __global__ __launch_bounds__(TN_NT) void k_tn_fwd(const T* __restrict__ in0, con
                                                   T* __restrict__ out0, T* __restrict__ out1, uint64_t in_bs,
                                                   uint64_t out_bs, uint64_t n_cols, uint64_t L)
 {
-    const uint64_t c = (uint64_t)blockIdx.x * TN_NT + threadIdx.x;
+    const TileWalk wk = xcd_tile_walk((uint32_t)((n_cols + TN_NT - 1) / TN_NT));
+    if (wk.first >= wk.end) return;
+    const uint64_t c = (uint64_t)wk.first * TN_NT + threadIdx.x;
     if (c >= n_cols) return;
     const T* in = (blockIdx.z == 0 ? in0 : in1) + (uint64_t)blockIdx.y * in_bs;
     T* out = (blockIdx.z == 0 ? out0 : out1) + (uint64_t)blockIdx.y * out_bs;
@@ -147,7 +149,9 @@ template <typename T, int M>
 __global__ __launch_bounds__(TN_NT) void k_tn_inv(const T* __restrict__ in, T* __restrict__ out, uint64_t in_bs,
                                                   uint64_t out_bs, uint64_t n_cols, uint64_t L)
 {
-    const uint64_t c = (uint64_t)blockIdx.x * TN_NT + threadIdx.x;
+    const TileWalk wk = xcd_tile_walk((uint32_t)((n_cols + TN_NT - 1) / TN_NT));
+    if (wk.first >= wk.end) return;
+    const uint64_t c = (uint64_t)wk.first * TN_NT + threadIdx.x;
     if (c >= n_cols) return;
     in += (uint64_t)blockIdx.y * in_bs;
     out += (uint64_t)blockIdx.y * out_bs;
@@ -306,8 +310,9 @@ __global__ __launch_bounds__(TN_INV3_NT) void k_tn_inv3w(const T* __restrict__ i
                                                          uint32_t tiles_per_hi, uint32_t n_tiles)
 {
     __shared__ T S[6 * 5 * 64];
-    const uint32_t tile = blockIdx.x;
-    if (tile >= n_tiles) return;  // the whole workgroup
+    const TileWalk wk = xcd_tile_walk(n_tiles);
+    if (wk.first >= wk.end) return;  // the whole workgroup
+    const uint32_t tile = wk.first;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     const uint32_t hi = tile / tiles_per_hi, j = tile - hi * tiles_per_hi;
@@ -474,7 +479,8 @@ template <typename T, int M>
 void launch_tn_fwd(const T* i0, const T* i1, T* o0, T* o1, uint64_t in_bs, uint64_t out_bs, uint64_t n_cols,
                    uint64_t L, int batch, hipStream_t s)
 {
-    dim3 grid((uint32_t)((n_cols + TN_NT - 1) / TN_NT), batch, 2);
+    const uint32_t nb = (uint32_t)((n_cols + TN_NT - 1) / TN_NT);
+    dim3 grid(nb >= 8 ? (nb + 7) & ~7u : nb, batch, 2);
     LaunchScope scope(s, 2.0 * batch * n_cols * (powc(3, M) + powc(6, M)) * sizeof(T), "tn_fwd<%s,M=%d>",
                       tname<T>(), M);
     k_tn_fwd<T, M><<<grid, TN_NT, 0, s>>>(i0, i1, o0, o1, in_bs, out_bs, n_cols, L);
@@ -484,7 +490,8 @@ template <typename T, int M>
 void launch_tn_inv(const T* in, T* out, uint64_t in_bs, uint64_t out_bs, uint64_t n_cols, uint64_t L, int batch,
                    hipStream_t s)
 {
-    dim3 grid((uint32_t)((n_cols + TN_NT - 1) / TN_NT), batch, 1);
+    const uint32_t nb = (uint32_t)((n_cols + TN_NT - 1) / TN_NT);
+    dim3 grid(nb >= 8 ? (nb + 7) & ~7u : nb, batch, 1);
     LaunchScope scope(s, (double)batch * n_cols * (powc(6, M) + powc(5, M)) * sizeof(T), "tn_inv<%s,M=%d>",
                       tname<T>(), M);
     k_tn_inv<T, M><<<grid, TN_NT, 0, s>>>(in, out, in_bs, out_bs, n_cols, L);
@@ -496,7 +503,7 @@ void launch_tn_inv3(const T* in, T* out, uint64_t in_bs, uint64_t out_bs, uint64
 {
     const uint32_t tiles_per_hi = (uint32_t)((L + 63) / 64);
     const uint32_t n_tiles = (uint32_t)(n_hi * tiles_per_hi);
-    dim3 grid(n_tiles, batch, 1);
+    dim3 grid(n_tiles >= 8 ? (n_tiles + 7) & ~7u : n_tiles, batch, 1);
     LaunchScope scope(s, (double)batch * n_hi * L * (216.0 + 125.0) * sizeof(T), "tn_inv<%s,M=3>", tname<T>());
     k_tn_inv3w<T><<<grid, TN_INV3_NT, 0, s>>>(in, out, in_bs, out_bs, L, tiles_per_hi, n_tiles);
 }
