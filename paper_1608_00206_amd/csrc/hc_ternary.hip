@@ -360,12 +360,16 @@ __global__ __launch_bounds__(TN_INV3_NT) void k_tn_inv3w(const T* __restrict__ i
 //            the product, U on axes 3, 2                         -> P[g0 g1][c2 c3]
 //   U01      25 threads (c2 c3): U on axes 1, 0, stored to z (a 25-entry
 //            run per output digit pair c0 c1)
-// P takes the memory of IN and F (after a barrier).
+// P takes the memory of IN and F (after a barrier).  The next group's rows
+// are loaded into registers while the current group is computed.
 constexpr int TN_TPB = 7;
 constexpr int TN_TILE_LDS = 900;  // 36 x 25 (P) >= 162 (IN) + 648 (F)
 
+// Held to three waves per SIMD (three workgroups per CU, as the 50 KB of LDS
+// allow): the registers of the next group's rows cost a few spills in
+// 8-byte types, which measured faster than two workgroups per CU.
 template <typename T>
-__global__ __launch_bounds__(TN_NT) void k_tn_tile4(const T* __restrict__ a, const T* __restrict__ b,
+__global__ __launch_bounds__(TN_NT) __attribute__((amdgpu_waves_per_eu(3))) void k_tn_tile4(const T* __restrict__ a, const T* __restrict__ b,
                                                     T* __restrict__ y, uint64_t in_bs, uint64_t y_bs,
                                                     uint32_t n_tiles)
 {
@@ -379,16 +383,37 @@ __global__ __launch_bounds__(TN_NT) void k_tn_tile4(const T* __restrict__ a, con
     const T* ai = a + item * in_bs;
     const T* bi = b + item * in_bs;
     T* yi = y + item * y_bs;
+    // the next group's rows are loaded into registers while this group is computed
+    constexpr int LPT = (TN_TPB * 162 + TN_NT - 1) / TN_NT;
+    T pre[LPT];
+    auto load_group = [&](uint32_t o0) {
+#pragma unroll
+        for (int j = 0; j < LPT; ++j) {
+            const int idx = tid + j * TN_NT;
+            T v = T(0);
+            if (idx < TN_TPB * 162) {
+                const int slot = idx / 162, r = idx - slot * 162;
+                const int op = r / 81, i = r - op * 81;
+                const uint32_t o = o0 + slot;
+                if (o < n_tiles) v = (op ? bi : ai)[(uint64_t)o * 81 + i];
+            }
+            pre[j] = v;
+        }
+    };
+    if (w.first < w.end) load_group(w.first * TN_TPB);
     for (uint32_t grp = w.first; grp < w.end; grp += w.step) {
         const uint32_t o0 = grp * TN_TPB;
         __syncthreads();  // the previous group's reads of S are done
-        // load: IN[slot][op][81]
-        for (int idx = tid; idx < TN_TPB * 162; idx += TN_NT) {
-            const int slot = idx / 162, r = idx - slot * 162;
-            const int op = r / 81, i = r - op * 81;
-            const uint32_t o = o0 + slot;
-            S[slot * TN_TILE_LDS + r] = o < n_tiles ? (op ? bi : ai)[(uint64_t)o * 81 + i] : T(0);
+        // IN[slot][op][81] from the registers, then the next group's loads
+#pragma unroll
+        for (int j = 0; j < LPT; ++j) {
+            const int idx = tid + j * TN_NT;
+            if (idx < TN_TPB * 162) {
+                const int slot = idx / 162, r = idx - slot * 162;
+                S[slot * TN_TILE_LDS + r] = pre[j];
+            }
         }
+        if (grp + w.step < w.end) load_group((grp + w.step) * TN_TPB);
         __syncthreads();
         T* tile = S + (ts < TN_TPB ? ts : 0) * TN_TILE_LDS;
         if (ts < TN_TPB && l < 18) {
