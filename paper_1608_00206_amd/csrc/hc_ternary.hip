@@ -360,14 +360,16 @@ __global__ __launch_bounds__(TN_INV3_NT) void k_tn_inv3w(const T* __restrict__ i
 //            the product, U on axes 3, 2                         -> P[g0 g1][c2 c3]
 //   U01      25 threads (c2 c3): U on axes 1, 0, stored to z (a 25-entry
 //            run per output digit pair c0 c1)
-// P takes the memory of IN and F (after a barrier).  The next group's rows
-// are loaded into registers while the current group is computed.
+// P takes the memory of IN and F (after a barrier).  A group's rows are
+// loaded into registers, every load in flight at once, and stored to LDS
+// after the barrier; when a workgroup runs several groups, the next group's
+// loads are issued while the current group computes.
 constexpr int TN_TPB = 7;
 constexpr int TN_TILE_LDS = 900;  // 36 x 25 (P) >= 162 (IN) + 648 (F)
 
 // Held to three waves per SIMD (three workgroups per CU, as the 50 KB of LDS
-// allow): the registers of the next group's rows cost a few spills in
-// 8-byte types, which measured faster than two workgroups per CU.
+// allow): the row registers cost a few spills in 8-byte types, which
+// measured faster than two workgroups per CU.
 template <typename T>
 __global__ __launch_bounds__(TN_NT) __attribute__((amdgpu_waves_per_eu(3))) void k_tn_tile4(const T* __restrict__ a, const T* __restrict__ b,
                                                     T* __restrict__ y, uint64_t in_bs, uint64_t y_bs,
@@ -383,7 +385,7 @@ __global__ __launch_bounds__(TN_NT) __attribute__((amdgpu_waves_per_eu(3))) void
     const T* ai = a + item * in_bs;
     const T* bi = b + item * in_bs;
     T* yi = y + item * y_bs;
-    // the next group's rows are loaded into registers while this group is computed
+    // a group's rows in registers (LPT per thread)
     constexpr int LPT = (TN_TPB * 162 + TN_NT - 1) / TN_NT;
     T pre[LPT];
     auto load_group = [&](uint32_t o0) {
