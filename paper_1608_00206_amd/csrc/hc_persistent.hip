@@ -76,10 +76,11 @@ __device__ __attribute__((noinline)) void single_tile(int K, const T* x, const T
     }
 }
 
-// The fused stage of a pair with p >= 1 outer axes: tile group g (waves
-// 3g .. 3g+2) runs the tiles [g, g + 1) * 3^(p-1) one after another, with the
-// next tile's rows loaded while the current tile is computed.  The groups run
-// the same number of tiles with the same code, so they meet at every barrier.
+// The fused stage of a pair with p >= 1 outer axes: tile group g (the
+// WAVES / GROUPS waves from g * WAVES / GROUPS on) runs the tiles
+// [g, g + 1) * 3^p / GROUPS one after another, with the next tile's rows
+// loaded while the current tile is computed.  The groups run the same number
+// of tiles with the same code, so they meet at every barrier.
 template <typename T>
 __device__ __forceinline__ void fused_stage(const T* xt, const T* yt, T* z, int p, int wave, T* S)
 {
@@ -199,11 +200,9 @@ __device__ __forceinline__ void run_pair(const PairPlan& pp, int D, const T* x, 
 // 4-byte elements: at most 96 registers, so that two workgroups share a CU.
 template <typename T>
 __global__ __launch_bounds__(PAIR_NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 5 : 1)))
-void k_pairs_persistent(const T* __restrict__ x, const T* __restrict__ y,
-                                                              T* z, T* ws, uint64_t slot_elems,
-                                                              const PairTask* __restrict__ tasks,
-                                                              const PairPlan* __restrict__ plans, uint32_t n_pairs,
-                                                              uint32_t* counters)
+void k_pairs_persistent(const T* __restrict__ x, const T* __restrict__ y, T* z, T* ws, uint64_t slot_elems,
+                        const PairTask* __restrict__ tasks, const PairPlan* __restrict__ plans, uint32_t n_pairs,
+                        uint32_t* counters)
 {
     __shared__ T S[PersistCfg<T>::LDS];
     __shared__ uint32_t s_ticket;
