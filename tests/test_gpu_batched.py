@@ -293,3 +293,27 @@ def test_more_pairs_than_one_launch_holds():
         plan.check()
         pins.assert_bitwise(Z.cpu().numpy(), want, f"70000 pairs {kw}")
         plan.close()
+
+
+@pytest.mark.parametrize("seed", [21, 22, 23])
+@pytest.mark.parametrize("dtype", [np.float64, np.float32, np.int64])
+def test_persistent_pairs_random_batches_equal_graph(dtype, seed):
+    """Random ragged batches (D from 0 to 13 in random order, repeats
+    included): the persistent launch and the grouped graph give the same
+    bits, and a sample of pairs equals the oracle."""
+    rng = np.random.default_rng(seed)
+    Ds = [int(d) for d in rng.integers(0, 14, int(rng.integers(1, 300)))]
+    print(f"random batch {np.dtype(dtype).name} seed={seed}: {len(Ds)} pairs", flush=True)
+    xs, ys = packed_inputs(Ds, dtype, seed=seed)
+    X = torch.from_numpy(np.concatenate(xs)).to(DEV)
+    Y = torch.from_numpy(np.concatenate(ys)).to(DEV)
+    tdt = NP2T[np.dtype(dtype)]
+    with hc.BatchedPlan(Ds, tdt) as g, hc.BatchedPlan(Ds, tdt, persistent_pairs=True) as p:
+        Zg = g.run(X, Y)
+        Zp = p.run(X, Y)
+        p.check()
+        Zg, Zp = Zg.cpu().numpy(), Zp.cpu().numpy()
+        pins.assert_bitwise(Zp, Zg, "persistent vs graph")
+        zo = p.z_offsets
+        for i in rng.choice(len(Ds), min(len(Ds), 4), replace=False):
+            pins.assert_bitwise(Zp[zo[i]:zo[i + 1]], oracle.canonical(xs[i], ys[i]), f"pair {i} D={Ds[i]}")
